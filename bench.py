@@ -1,0 +1,176 @@
+"""Benchmark of the FGraft harvest on one MI355X.
+
+A step is one whole build on the 1M x 128 uint8 workload (T=8 trees, B=8
+blocks, ef_h=64, R=32, alpha=1.2): scaffold, 8 x (harvest + merge),
+finalize.  The reported value is harvest distance evaluations per second
+(evaluations summed over the timed builds / harvest kernel time from HIP
+events on the build's stream); build seconds, recall@10 of the built graph
+and the roofline of the harvest kernel are reported beside it.  The data is
+synthetic (seeded clustered uint8 mixture) and resident in HBM before the
+timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2609_30493_amd import datagen as gen  # noqa: E402
+from paper_2609_30493_amd import fgraft as F  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def ground_truth_u8(xd: torch.Tensor, qd: torch.Tensor, k: int):
+    """Exact k-NN distances for uint8 rows: every quantity is an integer
+    below 2^24, so float32 products and sums are exact."""
+    xf = xd.float()
+    xn = (xf * xf).sum(1)
+    out = []
+    for s in range(0, qd.shape[0], 256):
+        qf = qd[s:s + 256].float()
+        d = (qf * qf).sum(1)[:, None] + xn[None, :] - 2.0 * (qf @ xf.T)
+        out.append(torch.topk(d, k, dim=1, largest=False).values)
+    return torch.cat(out)
+
+
+def recall_ladder(data, G, ws, qd, true_d, k=10, target=0.95):
+    res = []
+    nq = qd.shape[0]
+    for L in (10, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512):
+        oi = torch.empty(nq, k, dtype=torch.int32, device="cuda")
+        od = torch.empty(nq, k, dtype=torch.int32, device="cuda")
+        oe = torch.empty(nq, dtype=torch.int32, device="cuda")
+        F.search(data, G, qd, k, L, oi, od, oe, ws)
+        torch.cuda.synchronize()
+        found = od.cpu().numpy().view(np.uint32).astype(np.float64)
+        rec = float(np.mean(found <= true_d[:, -1:]))
+        res.append(dict(L=L, recall=rec, evals_per_query=float(oe.cpu().numpy().mean())))
+        if rec >= target:
+            break
+    return res
+
+
+def cpu_baseline(w, n_sample: int, threads: int):
+    """The oracle (plain C, untuned), whole build on a prefix-sized sample of
+    the same recipe and parameters; harvest evaluations per second."""
+    from oracle import fgo
+    x = gen.workload_data(w, n_sample)
+    P = fgo.params(w.T, w.ef_h, w.R, w.alpha, w.B, 0, threads)
+    t0 = time.perf_counter()
+    G = fgo.build_graph(fgo.Data(x), w.build_seed, P)
+    wall = time.perf_counter() - t0
+    c = G["counters"]
+    return {"value": c["harvest_evals"] / c["t_harvest"], "unit": "dist-evals/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"whole oracle build (scaffold, {w.B} blocks, finalize) on n={n_sample} "
+                      f"points of the same uint8 recipe, T={w.T} ef_h={w.ef_h} R={w.R}; "
+                      f"{wall:.1f} s wall, build {c['t_scaffold'] + c['t_harvest'] + c['t_merge'] + c['t_finalize']:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=None, help="override n (default: the workload's)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=100_000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the harvest would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    w = gen.CFG2
+    n = args.n or w.n
+    log(f"[bench] generating {n} x {w.d} uint8 rows")
+    x = gen.workload_data(w, n)
+    xd = torch.from_numpy(x).cuda()
+    data = F.make_data(xd)
+    params = F.make_params(w.T, w.ef_h, w.R, w.alpha, w.B)
+    ws = F.alloc_workspace(data, params)
+    log(f"[bench] workspace {ws.numel() / 2**30:.2f} GiB")
+
+    def u32(*shape):
+        return torch.full(shape, -1, dtype=torch.int32, device="cuda")
+
+    G = F.make_graph(u32(n, w.R), u32(n), u32(n), u32(w.T), w.T)
+
+    for i in range(args.warmup):
+        c, t = F.build_graph(data, w.build_seed, params, G, ws, timings=True)
+        log(f"[bench] warmup {i}: harvest {t['harvest_ms']:.1f} ms, scaffold {t['scaffold_ms']:.1f} ms")
+    torch.cuda.synchronize()
+    ev = hms = bms = 0.0
+    recs = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        c, t = F.build_graph(data, w.build_seed, params, G, ws, timings=True)
+        recs.append((c, t))
+        log(f"[bench] step {i}: harvest {t['harvest_ms']:.1f} ms scaffold {t['scaffold_ms']:.1f} ms "
+            f"merge {t['merge_ms']:.1f} ms finalize {t['finalize_ms']:.1f} ms")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for c, t in recs:
+        ev += c["harvest_evals"]
+        hms += t["harvest_ms"]
+    launches = len(recs) * len(recs[0][1]["block_harvest_ms"])
+    value = ev / (hms / 1e3)
+    row_bytes = w.d  # one uint8 row per evaluation
+    achieved = ev * row_bytes / (hms / 1e3) / 1e9
+    c0, t0_ = recs[0]
+    ghash = F.graph_hash(G)
+
+    out = {
+        "metric": "harvest dist-evals/s + build s at recall@10>=0.95; mixed/batched vs FP32",
+        "value": value,
+        "unit": "dist-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": n, "d": w.d, "T": w.T, "B": w.B, "ef_h": w.ef_h,
+                   "R": w.R, "alpha": w.alpha, "seed": w.build_seed},
+        "build_s": wall / args.steps,
+        "phase_ms": {k: t0_[k] for k in ("scaffold_ms", "harvest_ms", "merge_ms", "finalize_ms")},
+        "harvest_evals_per_build": c0["harvest_evals"],
+        "counters": c0,
+        "graph_hash": f"{ghash:#018x}",
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_beam (harvest)", "launches": launches,
+                     "bytes_per_eval": row_bytes},
+    }
+    if not args.no_recall:
+        qd = torch.from_numpy(gen.workload_queries(w)).cuda()
+        true_d = ground_truth_u8(xd, qd, 10).cpu().numpy().astype(np.float64)
+        lad = recall_ladder(data, G, ws, qd, true_d)
+        out["recall_ladder"] = lad
+        out["recall@10"] = lad[-1]["recall"]
+    if not args.no_cpu:
+        threads = min(16, os.cpu_count() or 1)
+        log(f"[bench] cpu baseline: oracle on {args.cpu_sample} points, {threads} threads")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, threads)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,213 @@
+/*
+ * fgraft.h -- C-ABI of the MI355X FGraft harvest library (libfgraft.so).
+ *
+ * FGraft (Sec. 3 of the paper) builds a navigable graph in B synchronous
+ * blocks.  S_0, the scaffold, is the union of the edges of T spatial-
+ * approximation trees, symmetrised.  For b = 0..B-1 every point p with
+ * p mod B == b beam-searches S_b with itself as the query (width ef_h, from
+ * the tree roots); the vertices the search expands are occlusion-pruned to
+ * at most R neighbours (slack alpha) into p's own row; then
+ * S_{b+1} = S_b u {(p,u),(u,p) : u in A[p], p in block b}.  The final graph
+ * is the harvested rows symmetrised and re-pruned, plus the tree-0 spine.
+ * By Prop. 1 the graph is a function of (data, seed, params, B) alone.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named *_dev are device (HIP) memory; everything else is host
+ *     memory.  Every buffer is owned by the caller; the library keeps no
+ *     allocation between calls.
+ *   - Work is enqueued on `stream` (a hipStream_t, NULL = default stream).
+ *     Entry points that return data-dependent sizes or counters synchronise
+ *     that stream before returning; they say so.
+ *   - `ws_dev` / `ws_bytes` is caller-allocated device scratch of at least
+ *     fg_workspace_size() bytes (256-byte aligned).  Two calls may run
+ *     concurrently only with distinct workspaces.
+ *   - Ids are uint32 (n < 2^32 - 1); 0xFFFFFFFF pads unused row slots.
+ *     CSR offsets are uint64.
+ *   - Errors: argument errors return before any work is enqueued; a HIP
+ *     failure returns FG_EHIP; a device-side capacity overflow returns
+ *     FG_ECAPACITY.  fg_last_error() gives a message for the calling thread.
+ *
+ * Distances (Sec. 3 does not fix the precision; the declared order makes the
+ * graph reproducible bit for bit):
+ *   FG_U8 + FG_L2SQ   exact int32 sum of squared differences;
+ *   FG_F32 + FG_L2SQ  float32, element chunk q of 4 goes to partial q mod 16,
+ *                     fused multiply-add per element, partials combined
+ *                     pairwise with offsets 8, 4, 2, 1;
+ *   FG_F32 + FG_COSINE  1 - <x, y> in the same order (rows pre-normalised).
+ * Candidates are totally ordered by (distance, id).
+ */
+#ifndef FGRAFT_H
+#define FGRAFT_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FG_OK = 0,
+  FG_EINVAL = -1,        /* bad argument */
+  FG_ENOMEM = -2,        /* workspace too small */
+  FG_EHIP = -3,          /* a HIP runtime call failed */
+  FG_ECAPACITY = -4,     /* a device-side bounded buffer overflowed */
+  FG_EUNSUPPORTED = -5   /* shape this build has no kernel for */
+} fg_status;
+
+typedef enum { FG_F32 = 0, FG_U8 = 1 } fg_dtype;
+typedef enum { FG_L2SQ = 0, FG_COSINE = 1 } fg_metric;
+
+/* Row-major data in device memory.  FG_F32 needs d % 4 == 0; FG_U8 needs
+ * d % 16 == 0 and FG_L2SQ.  row_stride_bytes is a multiple of 16 and at
+ * least d * element size. */
+typedef struct {
+  const void* x_dev;
+  int64_t n;
+  int32_t d;
+  int32_t dtype;   /* fg_dtype */
+  int32_t metric;  /* fg_metric */
+  int32_t reserved;
+  int64_t row_stride_bytes;
+} fg_data;
+
+/* Build parameters (Sec. 3).  B = 0 and B = 1 both mean one frozen block
+ * (frozen Graft).  reprune_all = 0 re-prunes in finalize only the rows whose
+ * symmetrised candidate set exceeds R; 1 re-prunes every row. */
+typedef struct {
+  uint32_t T;
+  uint32_t ef_h;
+  uint32_t R;
+  float alpha;
+  uint32_t B;
+  uint32_t reprune_all;
+  uint32_t reserved0;
+  uint32_t reserved1;
+} fg_params;
+
+/* Compressed rows in device memory: row v is ids_dev[off_dev[v] ..
+ * off_dev[v+1]), sorted by id, no repeats.  `cap` is the capacity of ids_dev
+ * (elements); `nnz` is a host copy of off_dev[n]. */
+typedef struct {
+  uint64_t* off_dev;
+  uint32_t* ids_dev;
+  int64_t n;
+  uint64_t nnz;
+  uint64_t cap;
+} fg_csr;
+
+/* The final graph, device memory: nbrs_dev is n x R (row p sorted by
+ * (d(p,.), id), 0xFFFFFFFF padded), cnt_dev[p] its length, spine_parent_dev
+ * tree 0's parent array (0xFFFFFFFF at its root), roots_dev the T roots. */
+typedef struct {
+  uint32_t* nbrs_dev;
+  uint32_t* cnt_dev;
+  uint32_t* spine_parent_dev;
+  uint32_t* roots_dev;
+  int64_t n;
+  uint32_t R;
+  uint32_t T;
+} fg_graph;
+
+/* Work counters (Sec. 2, "Cost model": every distance evaluation counts).
+ * harvest_evals is the number of vertices each harvest search visited
+ * (= evaluated), summed over points; prune_evals the pair distances the
+ * greedy prune needs (each later live candidate tested against each kept
+ * one until it dies). */
+typedef struct {
+  uint64_t scaffold_evals;
+  uint64_t harvest_evals;
+  uint64_t prune_evals;
+  uint64_t expansions;
+  uint64_t finalize_evals;
+  uint64_t spilled_queries; /* searches whose visited set left on-chip memory */
+} fg_counters;
+
+/* Per-phase device time (HIP events on `stream`), milliseconds. */
+typedef struct {
+  float scaffold_ms;
+  float harvest_ms;      /* sum over blocks */
+  float merge_ms;        /* sum over blocks */
+  float finalize_ms;
+  float block_harvest_ms[64];
+  uint64_t block_evals[64];
+  uint32_t nblocks;
+} fg_timings;
+
+/* Bytes of device scratch needed by every entry point below for this data
+ * shape and these parameters (one workspace serves all of them). */
+size_t fg_workspace_size(const fg_data* data, const fg_params* params);
+
+/* Keyed roots (Prop. 1, "keyed randomness"): root of tree t is the first
+ * draw splitmix64(seed, t * 2^32 + j) mod n, j = 0, 1, ..., not already a
+ * root, where splitmix64(seed, k) is output k of the SplitMix64 stream
+ * seeded with `seed`.  roots is a host array of T entries. */
+fg_status fg_roots(uint64_t seed, int64_t n, uint32_t T, uint32_t* roots);
+
+/* Scaffold S_0 (Sec. 1 and Sec. 3): T classic spatial-approximation trees
+ * rooted at roots_dev (distinct, device), the union of their parent-child
+ * edges in both directions.  Writes S0 (its off/ids buffers must hold n+1
+ * and 2*T*(n-1) entries; sets S0->nnz) and, when tree_parent_dev is not
+ * NULL, the T x n parent arrays.  Synchronises `stream`. */
+fg_status fg_build_scaffold(const fg_data* data, const uint32_t* roots_dev,
+                            uint32_t T, fg_csr* S0, uint32_t* tree_parent_dev,
+                            void* ws_dev, size_t ws_bytes, void* stream,
+                            fg_counters* counters);
+
+/* Harvest of block b (Sec. 3): for every p with p mod max(B,1) == b, the
+ * beam search of width ef_h over Sb from the T roots (roots_dev), then the
+ * occlusion prune of the expanded set minus p into rows_dev[p*R ..] (n x R)
+ * and row_cnt_dev[p].  Other rows are not touched.  counters (optional)
+ * makes the call synchronise `stream`. */
+fg_status fg_harvest_block(const fg_data* data, const fg_csr* Sb,
+                           const uint32_t* roots_dev, const fg_params* params,
+                           uint32_t b, uint32_t* rows_dev,
+                           uint32_t* row_cnt_dev, void* ws_dev, size_t ws_bytes,
+                           void* stream, fg_counters* counters);
+
+/* Union merge (Sec. 3): Sb1 = Sb u {(p,u),(u,p) : u in rows[p], p in block
+ * b}, rows sorted by id, deduplicated.  Sb1 must not alias Sb; its capacity
+ * must hold the result.  Synchronises `stream` (sets Sb1->nnz). */
+fg_status fg_merge_block(const fg_csr* Sb, const uint32_t* rows_dev,
+                         const uint32_t* row_cnt_dev, const fg_params* params,
+                         uint32_t b, fg_csr* Sb1, void* ws_dev, size_t ws_bytes,
+                         void* stream);
+
+/* Finalize (Sec. 3): for every p, Cand = A[p] u {u : p in A[u]}; when |Cand|
+ * exceeds R (or reprune_all) the occlusion prune of Cand, else Cand sorted
+ * by (d(p,.), id).  Writes graph->nbrs_dev and graph->cnt_dev only. */
+fg_status fg_finalize(const fg_data* data, const uint32_t* rows_dev,
+                      const uint32_t* row_cnt_dev, const fg_params* params,
+                      fg_graph* graph, void* ws_dev, size_t ws_bytes,
+                      void* stream, fg_counters* counters);
+
+/* The whole build (Sec. 3): roots from seed, scaffold, B x (harvest, merge),
+ * finalize.  Fills every array of `out` (its n, R, T must match).
+ * Synchronises `stream`.  timings (optional) records per-phase device time. */
+fg_status fg_build_graph(const fg_data* data, uint64_t seed,
+                         const fg_params* params, fg_graph* out, void* ws_dev,
+                         size_t ws_bytes, void* stream, fg_counters* counters,
+                         fg_timings* timings);
+
+/* Query search (Sec. 2, "quality"): beam of width L over G u spine from the
+ * roots for nq query rows (queries_dev, contiguous rows of d elements of the
+ * data's dtype); writes the first k entries per query: ids (nq x k), their
+ * distances (float32 for FG_F32, uint32 for FG_U8) and the evaluation count
+ * per query (optional).  Needs L >= k. */
+fg_status fg_search(const fg_data* data, const fg_graph* graph,
+                    const void* queries_dev, int64_t nq, uint32_t k,
+                    uint32_t L, uint32_t* out_ids_dev, void* out_dists_dev,
+                    uint32_t* out_evals_dev, void* ws_dev, size_t ws_bytes,
+                    void* stream);
+
+/* FNV-1a-64 over the graph's little-endian byte image: n (u64), R, T (u32),
+ * then per point its count and ids, then the spine parents, then the roots.
+ * Copies the graph to the host; synchronises `stream`. */
+fg_status fg_graph_hash(const fg_graph* graph, void* stream, uint64_t* out);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* fg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,692 @@
+// fg_api.hip -- the C-ABI of libfgraft.so: validation, workspace layout and
+// the orchestration of the kernels (Sec. 3 of the paper).
+#include <math.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "fg_internal.h"
+#include "fg_sat.h"
+
+namespace fg {
+
+namespace {
+thread_local std::string g_err;
+}
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+bool make_shape(const fg_data* d, Shape* s) {
+  if (!d || !d->x_dev) return set_error("data or data->x_dev is NULL"), false;
+  if (d->n < 1 || d->n >= (int64_t)FG_NONE) return set_error("n out of range"), false;
+  if (d->d < 1) return set_error("d must be positive"), false;
+  int64_t esz;
+  if (d->dtype == FG_F32) {
+    if (d->d % 4) return set_error("float32 rows need d % 4 == 0 (pad with zeros)"), false;
+    if (d->metric != FG_L2SQ && d->metric != FG_COSINE) return set_error("bad metric"), false;
+    esz = 4;
+    s->dk = d->metric == FG_COSINE ? F32COS : F32L2;
+    s->Q = d->d / 4;
+  } else if (d->dtype == FG_U8) {
+    if (d->d % 16) return set_error("uint8 rows need d % 16 == 0"), false;
+    if (d->metric != FG_L2SQ) return set_error("uint8 data supports squared L2 only"), false;
+    esz = 1;
+    s->dk = U8L2;
+    s->Q = d->d / 16;
+  } else {
+    return set_error("bad dtype"), false;
+  }
+  if (d->row_stride_bytes < esz * d->d || d->row_stride_bytes % 16)
+    return set_error("row_stride_bytes must be >= d * elem and a multiple of 16"), false;
+  if (reinterpret_cast<uintptr_t>(d->x_dev) % 16) return set_error("x_dev must be 16-byte aligned"), false;
+  s->x = static_cast<const uint8_t*>(d->x_dev);
+  s->stride = d->row_stride_bytes;
+  s->n = d->n;
+  s->d = d->d;
+  return true;
+}
+
+namespace {
+
+bool check_params(const fg_params* p, int64_t n, bool need_ef = true) {
+  if (!p) return set_error("params is NULL"), false;
+  if (p->T < 1 || (int64_t)p->T > n) return set_error("need 1 <= T <= n"), false;
+  if (p->T > 64) return set_error("T > 64 is not supported"), false;
+  if (need_ef && (p->ef_h < 1 || p->ef_h > (uint32_t)kMaxEfHarvest))
+    return set_error("need 1 <= ef_h <= 256"), false;
+  if (p->R < 1 || p->R > 1024) return set_error("need 1 <= R <= 1024"), false;
+  if (!isfinite(p->alpha) || p->alpha < 1.0f) return set_error("alpha must be finite and >= 1"), false;
+  return true;
+}
+
+uint32_t b_eff(const fg_params* p) { return p->B > 1 ? p->B : 1; }
+
+// ---------------------------------------------------------------- workspace
+// One layout serves every entry point for a given (n, T, R, B).
+struct WsMap {
+  size_t ctl, bits, slist, ebuf;            // beam kernels
+  size_t deg, cursor, newlen, aoff, noff, zoff, addbuf, tmp, scan;  // edge lists / merges
+  size_t sgoff, sgids;                      // search graph
+  size_t off[2], ids[2], rows, cnt, tparent, roots;  // the whole build
+  size_t sat;
+  SatWs satw;
+  size_t total;
+  int64_t spill_words;
+  uint64_t csr_cap, tmp_cap, add_cap;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+WsMap ws_map(int64_t n, const fg_params* p) {
+  WsMap m{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  const uint64_t T = p ? p->T : 1, R = p ? p->R : 1;
+  const uint64_t un = (uint64_t)n;
+  m.spill_words = (n + 31) / 32;
+  m.csr_cap = 2 * T * (un - 1) + 2 * R * un + 1;
+  m.add_cap = 2 * R * un + 2 * T * un + 1;
+  m.tmp_cap = m.csr_cap + m.add_cap;
+  m.ctl = take(4096);
+  m.bits = take((size_t)kMaxWaveSlots * m.spill_words * 4);
+  m.slist = take((size_t)kMaxWaveSlots * kSpillCap * 4);
+  m.ebuf = take((size_t)kMaxWaveSlots * kEcap * 8);
+  m.deg = take(un * 4);
+  m.cursor = take(un * 4);
+  m.newlen = take(un * 4);
+  m.aoff = take((un + 1) * 8);
+  m.noff = take((un + 1) * 8);
+  m.zoff = take((un + 1) * 8);
+  m.addbuf = take(m.add_cap * 4);
+  m.tmp = take(m.tmp_cap * 4);
+  m.scan = take(scan_scratch_bytes((int64_t)un + 1));
+  m.sgoff = take((un + 1) * 8);
+  m.sgids = take((R * un + 2 * un + 1) * 4);
+  for (int i = 0; i < 2; i++) {
+    m.off[i] = take((un + 1) * 8);
+    m.ids[i] = take(m.csr_cap * 4);
+  }
+  m.rows = take(R * un * 4);
+  m.cnt = take(un * 4);
+  m.tparent = take(T * un * 4);
+  m.roots = take(64 * 4);
+  sat_workspace_bytes(n, (uint32_t)T, &m.satw);
+  m.sat = take(m.satw.total);
+  m.total = o;
+  return m;
+}
+
+// ctl region: [0] queue, [1..4] beam counters, [8] status (int)
+struct Ctl {
+  unsigned long long queue;
+  unsigned long long counters[4];    // beam: evals, expansions, prune pairs, spilled
+  unsigned long long fin[2];         // finalize: candidate distances, prune pairs
+  unsigned long long pad;
+  int status;                        // 1 expanded-set, 2 merge-row, 4 finalize-row overflow
+};
+
+hipError_t g_last_hip = hipSuccess;
+#define FG_HIP(call)                                                           \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      g_last_hip = e_;                                                         \
+      set_error(std::string("HIP error: ") + hipGetErrorString(e_) + " at " + #call); \
+      return FG_EHIP;                                                          \
+    }                                                                          \
+  } while (0)
+
+bool check_ws(void* ws, size_t ws_bytes, const WsMap& m) {
+  if (!ws) return set_error("workspace is NULL"), false;
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return set_error("workspace must be 256-byte aligned"), false;
+  if (ws_bytes < m.total) return set_error("workspace too small (see fg_workspace_size)"), false;
+  return true;
+}
+
+char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
+
+// Launch the harvest of block b.  The spill bitsets must be zero on entry
+// (they are left zero on exit).
+fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* ids,
+                         const uint32_t* roots, const fg_params* P, uint32_t b, uint32_t* rows,
+                         uint32_t* cnt, void* ws, const WsMap& m, hipStream_t st) {
+  const uint32_t Be = b_eff(P);
+  int64_t nitems = s.n > (int64_t)b ? (s.n - (int64_t)b + Be - 1) / Be : 0;
+  Ctl* ctl = reinterpret_cast<Ctl*>(at(ws, m.ctl));
+  FG_HIP(fill_u64(reinterpret_cast<uint64_t*>(&ctl->queue), 0, 1, st));
+  if (nitems == 0) return FG_OK;
+  int grid = beam_grid(s, (int)P->ef_h, false);
+  if (grid <= 0) return set_error("no beam kernel for this row size / ef_h"), FG_EUNSUPPORTED;
+  BeamArgs a{};
+  a.x = s.x;
+  a.stride = s.stride;
+  a.n = s.n;
+  a.Q = s.Q;
+  a.off = off;
+  a.ids = ids;
+  a.roots = roots;
+  a.T = (int)P->T;
+  a.ef = (int)P->ef_h;
+  a.R = (int)P->R;
+  a.alpha = P->alpha;
+  a.b = b;
+  a.B = Be;
+  a.rows = rows;
+  a.cnt = cnt;
+  a.nitems = nitems;
+  a.queue = &ctl->queue;
+  a.Ebuf = reinterpret_cast<uint64_t*>(at(ws, m.ebuf));
+  a.Ecap = kEcap;
+  a.spill_bits = reinterpret_cast<uint32_t*>(at(ws, m.bits));
+  a.spill_words = m.spill_words;
+  a.spill_list = reinterpret_cast<uint32_t*>(at(ws, m.slist));
+  a.spill_cap = kSpillCap;
+  a.counters = ctl->counters;
+  a.status = &ctl->status;
+  FG_HIP(launch_beam(s, a, false, grid, st));
+  return FG_OK;
+}
+
+fg_status reset_ctl(void* ws, const WsMap& m, hipStream_t st) {
+  FG_HIP(fill_u64(reinterpret_cast<uint64_t*>(at(ws, m.ctl)), 0, 4096 / 8, st));
+  return FG_OK;
+}
+
+fg_status read_ctl(void* ws, const WsMap& m, hipStream_t st, Ctl* out) {
+  FG_HIP(hipMemcpyAsync(out, at(ws, m.ctl), sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  FG_HIP(hipStreamSynchronize(st));
+  return FG_OK;
+}
+
+// S_{b+1} = S_b u rows of block b (both directions), sorted and deduplicated
+// per row.  Leaves the new offsets in off1 (off1[n] = nnz) and the ids in
+// ids1; the caller guarantees the capacity.
+fg_status merge_launch(int64_t n, const uint64_t* off0, const uint32_t* ids0, const uint32_t* rows,
+                       const uint32_t* cnt, int R, uint32_t b, uint32_t Be, uint64_t* off1,
+                       uint32_t* ids1, void* ws, const WsMap& m, hipStream_t st) {
+  int64_t nitems = n > (int64_t)b ? (n - (int64_t)b + Be - 1) / Be : 0;
+  uint32_t* deg = reinterpret_cast<uint32_t*>(at(ws, m.deg));
+  uint32_t* cursor = reinterpret_cast<uint32_t*>(at(ws, m.cursor));
+  uint32_t* newlen = reinterpret_cast<uint32_t*>(at(ws, m.newlen));
+  uint64_t* aoff = reinterpret_cast<uint64_t*>(at(ws, m.aoff));
+  uint32_t* addbuf = reinterpret_cast<uint32_t*>(at(ws, m.addbuf));
+  uint32_t* tmp = reinterpret_cast<uint32_t*>(at(ws, m.tmp));
+  void* scan = at(ws, m.scan);
+  Ctl* ctl = reinterpret_cast<Ctl*>(at(ws, m.ctl));
+  FG_HIP(fill_u32(deg, 0, n, st));
+  FG_HIP(edges_count(n, rows, cnt, R, b, Be, nitems, true, true, deg, st));
+  FG_HIP(exclusive_scan_u32_u64(deg, aoff, n, scan, st));
+  FG_HIP(fill_u32(cursor, 0, n, st));
+  FG_HIP(edges_scatter(n, rows, cnt, R, b, Be, nitems, true, true, aoff, cursor, addbuf, st));
+  FG_HIP(merge_rows(n, off0, ids0, aoff, addbuf, tmp, newlen, &ctl->status, st));
+  FG_HIP(exclusive_scan_u32_u64(newlen, off1, n, scan, st));
+  FG_HIP(compact_rows(n, off0, aoff, tmp, off1, ids1, st));
+  return FG_OK;
+}
+
+// S_0 from the T parent arrays: both directions of every tree edge, sorted
+// and deduplicated per row.
+fg_status scaffold_csr_launch(int64_t n, uint32_t T, const uint32_t* tparent, uint64_t* off,
+                              uint32_t* ids, void* ws, const WsMap& m, hipStream_t st) {
+  uint32_t* deg = reinterpret_cast<uint32_t*>(at(ws, m.deg));
+  uint32_t* cursor = reinterpret_cast<uint32_t*>(at(ws, m.cursor));
+  uint32_t* newlen = reinterpret_cast<uint32_t*>(at(ws, m.newlen));
+  uint64_t* aoff = reinterpret_cast<uint64_t*>(at(ws, m.aoff));
+  uint64_t* zoff = reinterpret_cast<uint64_t*>(at(ws, m.zoff));
+  uint32_t* addbuf = reinterpret_cast<uint32_t*>(at(ws, m.addbuf));
+  uint32_t* tmp = reinterpret_cast<uint32_t*>(at(ws, m.tmp));
+  void* scan = at(ws, m.scan);
+  Ctl* ctl = reinterpret_cast<Ctl*>(at(ws, m.ctl));
+  FG_HIP(tree_edges_csr(n, T, tparent, deg, aoff, cursor, addbuf, st, scan));
+  FG_HIP(fill_u64(zoff, 0, n + 1, st));
+  FG_HIP(merge_rows(n, zoff, addbuf, aoff, addbuf, tmp, newlen, &ctl->status, st));
+  FG_HIP(exclusive_scan_u32_u64(newlen, off, n, scan, st));
+  FG_HIP(compact_rows(n, zoff, aoff, tmp, off, ids, st));
+  return FG_OK;
+}
+
+fg_status finalize_launch(const Shape& s, const uint32_t* rows, const uint32_t* cnt, const fg_params* P,
+                          uint32_t* g_nbrs, uint32_t* g_cnt, void* ws, const WsMap& m, hipStream_t st) {
+  const int64_t n = s.n;
+  const int R = (int)P->R;
+  uint32_t* deg = reinterpret_cast<uint32_t*>(at(ws, m.deg));
+  uint32_t* cursor = reinterpret_cast<uint32_t*>(at(ws, m.cursor));
+  uint64_t* aoff = reinterpret_cast<uint64_t*>(at(ws, m.aoff));
+  uint32_t* addbuf = reinterpret_cast<uint32_t*>(at(ws, m.addbuf));
+  void* scan = at(ws, m.scan);
+  Ctl* ctl = reinterpret_cast<Ctl*>(at(ws, m.ctl));
+  FG_HIP(fill_u32(deg, 0, n, st));
+  FG_HIP(edges_count(n, rows, cnt, R, 0, 1, n, false, true, deg, st));
+  FG_HIP(exclusive_scan_u32_u64(deg, aoff, n, scan, st));
+  FG_HIP(fill_u32(cursor, 0, n, st));
+  FG_HIP(edges_scatter(n, rows, cnt, R, 0, 1, n, false, true, aoff, cursor, addbuf, st));
+  FinalizeArgs f{};
+  f.X = RowSet{s.x, s.stride, s.Q};
+  f.n = n;
+  f.R = R;
+  f.alpha = P->alpha;
+  f.reprune_all = P->reprune_all ? 1 : 0;
+  f.rows = rows;
+  f.cnt = cnt;
+  f.revoff = aoff;
+  f.rev = addbuf;
+  f.g_nbrs = g_nbrs;
+  f.g_cnt = g_cnt;
+  f.counters = ctl->fin;
+  f.status = &ctl->status;
+  FG_HIP(launch_finalize(s.dk, s.Q, f, st));
+  return FG_OK;
+}
+
+fg_status status_error(int status) {
+  if (status & 1) return set_error("a search expanded more vertices than its capacity"), FG_ECAPACITY;
+  if (status & 2) return set_error("a row gained more than 2048 edges in one merge"), FG_ECAPACITY;
+  if (status & 4) return set_error("a point has more than 2048 finalize candidates"), FG_ECAPACITY;
+  if (status & 8) return set_error("the tree builder's segment list overflowed"), FG_ECAPACITY;
+  return FG_OK;
+}
+
+uint64_t splitmix64(uint64_t seed, uint64_t k) {
+  // Output k of the SplitMix64 stream (Steele, Lea and Flood 2014).
+  uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+}  // namespace
+}  // namespace fg
+
+using namespace fg;
+
+extern "C" {
+
+const char* fg_last_error(void) { return g_err.c_str(); }
+
+size_t fg_workspace_size(const fg_data* data, const fg_params* params) {
+  if (!data || data->n < 1) return 0;
+  return ws_map(data->n, params).total;
+}
+
+fg_status fg_roots(uint64_t seed, int64_t n, uint32_t T, uint32_t* roots) {
+  if (!roots || n < 1 || T < 1 || (int64_t)T > n) {
+    set_error("fg_roots: need roots != NULL and 1 <= T <= n");
+    return FG_EINVAL;
+  }
+  for (uint32_t t = 0; t < T; t++) {
+    for (uint64_t j = 0;; j++) {
+      uint32_t r = (uint32_t)(splitmix64(seed, ((uint64_t)t << 32) + j) % (uint64_t)n);
+      bool dup = false;
+      for (uint32_t u = 0; u < t; u++) dup = dup || roots[u] == r;
+      if (!dup) {
+        roots[t] = r;
+        break;
+      }
+    }
+  }
+  return FG_OK;
+}
+
+fg_status fg_harvest_block(const fg_data* data, const fg_csr* Sb, const uint32_t* roots_dev,
+                           const fg_params* params, uint32_t b, uint32_t* rows_dev,
+                           uint32_t* row_cnt_dev, void* ws_dev, size_t ws_bytes, void* stream,
+                           fg_counters* counters) {
+  Shape s;
+  if (!make_shape(data, &s)) return FG_EINVAL;
+  if (!check_params(params, s.n)) return FG_EINVAL;
+  if (!Sb || !Sb->off_dev || !Sb->ids_dev || Sb->n != s.n)
+    return set_error("Sb must be a CSR over the data's n points"), FG_EINVAL;
+  if (!roots_dev || !rows_dev || !row_cnt_dev) return set_error("NULL output or roots"), FG_EINVAL;
+  if (b >= b_eff(params)) return set_error("need b < max(B, 1)"), FG_EINVAL;
+  WsMap m = ws_map(s.n, params);
+  if (!check_ws(ws_dev, ws_bytes, m)) return FG_ENOMEM;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  fg_status r = reset_ctl(ws_dev, m, st);
+  if (r) return r;
+  FG_HIP(fill_u32(reinterpret_cast<uint32_t*>(at(ws_dev, m.bits)), 0,
+                  (int64_t)kMaxWaveSlots * m.spill_words, st));
+  r = harvest_launch(s, Sb->off_dev, Sb->ids_dev, roots_dev, params, b, rows_dev, row_cnt_dev, ws_dev,
+                     m, st);
+  if (r) return r;
+  if (counters) {
+    Ctl c;
+    r = read_ctl(ws_dev, m, st, &c);
+    if (r) return r;
+    counters->harvest_evals += c.counters[0];
+    counters->expansions += c.counters[1];
+    counters->prune_evals += c.counters[2];
+    counters->spilled_queries += c.counters[3];
+    return status_error(c.status);
+  }
+  return FG_OK;
+}
+
+fg_status fg_build_scaffold(const fg_data* data, const uint32_t* roots_dev, uint32_t T, fg_csr* S0,
+                            uint32_t* tree_parent_dev, void* ws_dev, size_t ws_bytes, void* stream,
+                            fg_counters* counters) {
+  Shape s;
+  if (!make_shape(data, &s)) return FG_EINVAL;
+  if (T < 1 || (int64_t)T > s.n || T > 64) return set_error("need 1 <= T <= min(n, 64)"), FG_EINVAL;
+  if (!roots_dev || !S0 || !S0->off_dev || !S0->ids_dev || S0->n != s.n)
+    return set_error("roots_dev and an S0 CSR over n points are required"), FG_EINVAL;
+  if (S0->cap < 2ull * T * (uint64_t)(s.n - 1)) return set_error("S0->cap < 2*T*(n-1)"), FG_EINVAL;
+  fg_params P{};
+  P.T = T;
+  P.ef_h = 1;
+  P.R = 1;
+  P.alpha = 1.0f;
+  WsMap m = ws_map(s.n, &P);
+  if (!check_ws(ws_dev, ws_bytes, m)) return FG_ENOMEM;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  fg_status r = reset_ctl(ws_dev, m, st);
+  if (r) return r;
+  uint32_t* tparent = tree_parent_dev ? tree_parent_dev : reinterpret_cast<uint32_t*>(at(ws_dev, m.tparent));
+  unsigned long long evals = 0;
+  int status = 0;
+  FG_HIP(sat_build(s, roots_dev, T, tparent, at(ws_dev, m.sat), m.satw, st, &evals, &status));
+  if (status) return status_error(status);
+  r = scaffold_csr_launch(s.n, T, tparent, S0->off_dev, S0->ids_dev, ws_dev, m, st);
+  if (r) return r;
+  Ctl c;
+  r = read_ctl(ws_dev, m, st, &c);
+  if (r) return r;
+  FG_HIP(hipMemcpyAsync(&S0->nnz, S0->off_dev + s.n, 8, hipMemcpyDeviceToHost, st));
+  FG_HIP(hipStreamSynchronize(st));
+  if (counters) counters->scaffold_evals += evals;
+  return status_error(c.status);
+}
+
+fg_status fg_merge_block(const fg_csr* Sb, const uint32_t* rows_dev, const uint32_t* row_cnt_dev,
+                         const fg_params* params, uint32_t b, fg_csr* Sb1, void* ws_dev, size_t ws_bytes,
+                         void* stream) {
+  if (!Sb || !Sb1 || !Sb->off_dev || !Sb->ids_dev || !Sb1->off_dev || !Sb1->ids_dev)
+    return set_error("Sb and Sb1 must be CSRs"), FG_EINVAL;
+  if (Sb->n != Sb1->n || Sb->n < 1) return set_error("Sb and Sb1 must have the same n"), FG_EINVAL;
+  if (Sb->ids_dev == Sb1->ids_dev || Sb->off_dev == Sb1->off_dev)
+    return set_error("Sb1 must not alias Sb"), FG_EINVAL;
+  if (!check_params(params, Sb->n, false)) return FG_EINVAL;
+  if (!rows_dev || !row_cnt_dev) return set_error("rows and row counts are required"), FG_EINVAL;
+  const uint32_t Be = b_eff(params);
+  if (b >= Be) return set_error("need b < max(B, 1)"), FG_EINVAL;
+  WsMap m = ws_map(Sb->n, params);
+  if (!check_ws(ws_dev, ws_bytes, m)) return FG_ENOMEM;
+  const int64_t n = Sb->n;
+  int64_t nitems = n > (int64_t)b ? (n - (int64_t)b + Be - 1) / Be : 0;
+  if (Sb->nnz + 2ull * params->R * (uint64_t)nitems > m.tmp_cap)
+    return set_error("Sb->nnz exceeds what this workspace was sized for"), FG_ENOMEM;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  fg_status r = reset_ctl(ws_dev, m, st);
+  if (r) return r;
+  uint64_t* noff = reinterpret_cast<uint64_t*>(at(ws_dev, m.noff));
+  uint32_t* scratch_ids = reinterpret_cast<uint32_t*>(at(ws_dev, m.ids[0]));
+  // merge into the workspace first, then check the caller's capacity
+  r = merge_launch(n, Sb->off_dev, Sb->ids_dev, rows_dev, row_cnt_dev, (int)params->R, b, Be, noff,
+                   scratch_ids, ws_dev, m, st);
+  if (r) return r;
+  uint64_t nnz = 0;
+  Ctl c;
+  FG_HIP(hipMemcpyAsync(&nnz, noff + n, 8, hipMemcpyDeviceToHost, st));
+  r = read_ctl(ws_dev, m, st, &c);
+  if (r) return r;
+  if (c.status) return status_error(c.status);
+  if (nnz > Sb1->cap) return set_error("Sb1->cap is too small for the merged substrate"), FG_ECAPACITY;
+  FG_HIP(hipMemcpyAsync(Sb1->off_dev, noff, (n + 1) * 8, hipMemcpyDeviceToDevice, st));
+  FG_HIP(hipMemcpyAsync(Sb1->ids_dev, scratch_ids, nnz * 4, hipMemcpyDeviceToDevice, st));
+  FG_HIP(hipStreamSynchronize(st));
+  Sb1->nnz = nnz;
+  return FG_OK;
+}
+
+fg_status fg_finalize(const fg_data* data, const uint32_t* rows_dev, const uint32_t* row_cnt_dev,
+                      const fg_params* params, fg_graph* graph, void* ws_dev, size_t ws_bytes, void* stream,
+                      fg_counters* counters) {
+  Shape s;
+  if (!make_shape(data, &s)) return FG_EINVAL;
+  if (!check_params(params, s.n, false)) return FG_EINVAL;
+  if (!rows_dev || !row_cnt_dev || !graph || !graph->nbrs_dev || !graph->cnt_dev)
+    return set_error("rows, counts and graph arrays are required"), FG_EINVAL;
+  if (graph->n != s.n || graph->R != params->R) return set_error("graph shape mismatch"), FG_EINVAL;
+  WsMap m = ws_map(s.n, params);
+  if (!check_ws(ws_dev, ws_bytes, m)) return FG_ENOMEM;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  fg_status r = reset_ctl(ws_dev, m, st);
+  if (r) return r;
+  r = finalize_launch(s, rows_dev, row_cnt_dev, params, graph->nbrs_dev, graph->cnt_dev, ws_dev, m, st);
+  if (r) return r;
+  if (counters) {
+    Ctl c;
+    r = read_ctl(ws_dev, m, st, &c);
+    if (r) return r;
+    counters->finalize_evals += c.fin[0] + c.fin[1];
+    return status_error(c.status);
+  }
+  return FG_OK;
+}
+
+fg_status fg_search(const fg_data* data, const fg_graph* graph, const void* queries_dev, int64_t nq,
+                    uint32_t k, uint32_t L, uint32_t* out_ids_dev, void* out_dists_dev,
+                    uint32_t* out_evals_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+  Shape s;
+  if (!make_shape(data, &s)) return FG_EINVAL;
+  if (!graph || !graph->nbrs_dev || !graph->cnt_dev || !graph->spine_parent_dev || !graph->roots_dev ||
+      graph->n != s.n || graph->T < 1 || graph->T > 64 || graph->R < 1)
+    return set_error("graph is incomplete or does not match the data"), FG_EINVAL;
+  if (!queries_dev || nq < 0 || !out_ids_dev || !out_dists_dev)
+    return set_error("queries and outputs are required"), FG_EINVAL;
+  if (reinterpret_cast<uintptr_t>(queries_dev) % 16) return set_error("queries must be 16-byte aligned"), FG_EINVAL;
+  if (k < 1 || L < k || L > (uint32_t)kMaxEfSearch) return set_error("need 1 <= k <= L <= 512"), FG_EINVAL;
+  fg_params P{};
+  P.T = graph->T;
+  P.R = graph->R;
+  P.ef_h = 1;
+  P.alpha = 1.0f;
+  WsMap m = ws_map(s.n, &P);
+  if (!check_ws(ws_dev, ws_bytes, m)) return FG_ENOMEM;
+  if (nq == 0) return FG_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  fg_status r = reset_ctl(ws_dev, m, st);
+  if (r) return r;
+  uint64_t* sgoff = reinterpret_cast<uint64_t*>(at(ws_dev, m.sgoff));
+  uint32_t* sgids = reinterpret_cast<uint32_t*>(at(ws_dev, m.sgids));
+  FG_HIP(search_graph(s.n, (int)graph->R, graph->nbrs_dev, graph->cnt_dev, graph->spine_parent_dev,
+                      reinterpret_cast<uint32_t*>(at(ws_dev, m.deg)), sgoff, sgids, at(ws_dev, m.scan), st));
+  FG_HIP(fill_u32(reinterpret_cast<uint32_t*>(at(ws_dev, m.bits)), 0, (int64_t)kMaxWaveSlots * m.spill_words, st));
+  int grid = beam_grid(s, (int)L, true);
+  if (grid <= 0) return set_error("no search kernel for this row size / L"), FG_EUNSUPPORTED;
+  Ctl* ctl = reinterpret_cast<Ctl*>(at(ws_dev, m.ctl));
+  BeamArgs a{};
+  a.x = s.x;
+  a.stride = s.stride;
+  a.n = s.n;
+  a.Q = s.Q;
+  a.off = sgoff;
+  a.ids = sgids;
+  a.roots = graph->roots_dev;
+  a.T = (int)graph->T;
+  a.ef = (int)L;
+  a.queries = static_cast<const uint8_t*>(queries_dev);
+  a.qstride = (int64_t)s.d * (data->dtype == FG_F32 ? 4 : 1);
+  a.k = (int)k;
+  a.out_ids = out_ids_dev;
+  a.out_d = out_dists_dev;
+  a.out_evals = out_evals_dev;
+  a.nitems = nq;
+  a.queue = &ctl->queue;
+  a.Ebuf = reinterpret_cast<uint64_t*>(at(ws_dev, m.ebuf));
+  a.Ecap = kEcap;
+  a.spill_bits = reinterpret_cast<uint32_t*>(at(ws_dev, m.bits));
+  a.spill_words = m.spill_words;
+  a.spill_list = reinterpret_cast<uint32_t*>(at(ws_dev, m.slist));
+  a.spill_cap = kSpillCap;
+  a.counters = ctl->counters;
+  a.status = &ctl->status;
+  FG_HIP(launch_beam(s, a, true, grid, st));
+  return FG_OK;
+}
+
+fg_status fg_graph_hash(const fg_graph* graph, void* stream, uint64_t* out) {
+  if (!graph || !out || !graph->nbrs_dev || !graph->cnt_dev || !graph->spine_parent_dev || !graph->roots_dev ||
+      graph->n < 1)
+    return set_error("incomplete graph"), FG_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t n = graph->n;
+  const uint32_t R = graph->R, T = graph->T;
+  std::vector<uint32_t> nb((size_t)n * R), cnt(n), par(n), roots(T);
+  FG_HIP(hipMemcpyAsync(nb.data(), graph->nbrs_dev, nb.size() * 4, hipMemcpyDeviceToHost, st));
+  FG_HIP(hipMemcpyAsync(cnt.data(), graph->cnt_dev, cnt.size() * 4, hipMemcpyDeviceToHost, st));
+  FG_HIP(hipMemcpyAsync(par.data(), graph->spine_parent_dev, par.size() * 4, hipMemcpyDeviceToHost, st));
+  FG_HIP(hipMemcpyAsync(roots.data(), graph->roots_dev, roots.size() * 4, hipMemcpyDeviceToHost, st));
+  FG_HIP(hipStreamSynchronize(st));
+  // FNV-1a, 64-bit, over the little-endian byte image.
+  uint64_t h = 0xCBF29CE484222325ull;
+  auto feed = [&](const void* p, size_t len) {
+    const uint8_t* b = static_cast<const uint8_t*>(p);
+    for (size_t i = 0; i < len; i++) {
+      h ^= b[i];
+      h *= 0x100000001B3ull;
+    }
+  };
+  uint64_t n64 = (uint64_t)n;
+  feed(&n64, 8);
+  feed(&R, 4);
+  feed(&T, 4);
+  for (int64_t p = 0; p < n; p++) {
+    if (cnt[p] > R) return set_error("row count above R"), FG_EINVAL;
+    feed(&cnt[p], 4);
+    feed(&nb[(size_t)p * R], (size_t)cnt[p] * 4);
+  }
+  feed(par.data(), par.size() * 4);
+  feed(roots.data(), roots.size() * 4);
+  *out = h;
+  return FG_OK;
+}
+
+fg_status fg_build_graph(const fg_data* data, uint64_t seed, const fg_params* params, fg_graph* out,
+                         void* ws_dev, size_t ws_bytes, void* stream, fg_counters* counters,
+                         fg_timings* timings) {
+  Shape s;
+  if (!make_shape(data, &s)) return FG_EINVAL;
+  if (!check_params(params, s.n)) return FG_EINVAL;
+  if (!out || !out->nbrs_dev || !out->cnt_dev || !out->spine_parent_dev || !out->roots_dev)
+    return set_error("every array of the output graph is required"), FG_EINVAL;
+  if (out->n != s.n || out->R != params->R || out->T != params->T)
+    return set_error("output graph shape does not match data/params"), FG_EINVAL;
+  const uint32_t Be = b_eff(params);
+  if (timings && Be > 64) return set_error("timings record at most 64 blocks"), FG_EINVAL;
+  WsMap m = ws_map(s.n, params);
+  if (!check_ws(ws_dev, ws_bytes, m)) return FG_ENOMEM;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t n = s.n;
+  const uint32_t T = params->T, R = params->R;
+
+  std::vector<hipEvent_t> ev;
+  auto mark = [&]() -> fg_status {
+    if (!timings) return FG_OK;
+    hipEvent_t e;
+    FG_HIP(hipEventCreate(&e));
+    FG_HIP(hipEventRecord(e, st));
+    ev.push_back(e);
+    return FG_OK;
+  };
+  auto cleanup = [&]() {
+    for (auto e : ev) hipEventDestroy(e);
+  };
+  fg_status r;
+#define FG_TRY(x)       do {                    r = (x);              if (r) {                cleanup();            return r;           }                   } while (0)
+
+  std::vector<uint32_t> hroots(T);
+  FG_TRY(fg_roots(seed, n, T, hroots.data()));
+  FG_TRY(reset_ctl(ws_dev, m, st));
+  uint32_t* roots = out->roots_dev;
+  FG_HIP(hipMemcpyAsync(roots, hroots.data(), T * 4, hipMemcpyHostToDevice, st));
+  uint32_t* tparent = reinterpret_cast<uint32_t*>(at(ws_dev, m.tparent));
+  uint64_t* off[2] = {reinterpret_cast<uint64_t*>(at(ws_dev, m.off[0])),
+                      reinterpret_cast<uint64_t*>(at(ws_dev, m.off[1]))};
+  uint32_t* ids[2] = {reinterpret_cast<uint32_t*>(at(ws_dev, m.ids[0])),
+                      reinterpret_cast<uint32_t*>(at(ws_dev, m.ids[1]))};
+  uint32_t* rows = reinterpret_cast<uint32_t*>(at(ws_dev, m.rows));
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(at(ws_dev, m.cnt));
+
+  // Scaffold.
+  FG_TRY(mark());
+  unsigned long long sat_evals = 0;
+  int status = 0;
+  FG_HIP(sat_build(s, roots, T, tparent, at(ws_dev, m.sat), m.satw, st, &sat_evals, &status));
+  if (status) {
+    cleanup();
+    return status_error(status);
+  }
+  FG_TRY(scaffold_csr_launch(n, T, tparent, off[0], ids[0], ws_dev, m, st));
+  FG_HIP(hipMemcpyAsync(out->spine_parent_dev, tparent, n * 4, hipMemcpyDeviceToDevice, st));
+  FG_TRY(mark());
+
+  // Blocks.
+  FG_HIP(fill_u32(rows, FG_NONE, n * (int64_t)R, st));
+  FG_HIP(fill_u32(cnt, 0, n, st));
+  FG_HIP(fill_u32(reinterpret_cast<uint32_t*>(at(ws_dev, m.bits)), 0, (int64_t)kMaxWaveSlots * m.spill_words, st));
+  int cur = 0;
+  std::vector<unsigned long long> blk_evals;
+  Ctl* ctl = reinterpret_cast<Ctl*>(at(ws_dev, m.ctl));
+  for (uint32_t b = 0; b < Be; b++) {
+    FG_TRY(mark());
+    FG_TRY(harvest_launch(s, off[cur], ids[cur], roots, params, b, rows, cnt, ws_dev, m, st));
+    FG_TRY(mark());
+    if (timings) {
+      unsigned long long e = 0;
+      FG_HIP(hipMemcpyAsync(&e, &ctl->counters[0], 8, hipMemcpyDeviceToHost, st));
+      FG_HIP(hipStreamSynchronize(st));
+      blk_evals.push_back(e);
+    }
+    if (b + 1 < Be) {
+      FG_TRY(merge_launch(n, off[cur], ids[cur], rows, cnt, (int)R, b, Be, off[cur ^ 1], ids[cur ^ 1], ws_dev,
+                          m, st));
+      cur ^= 1;
+    }
+    FG_TRY(mark());
+  }
+
+  // Finalize.
+  FG_TRY(finalize_launch(s, rows, cnt, params, out->nbrs_dev, out->cnt_dev, ws_dev, m, st));
+  FG_TRY(mark());
+  Ctl c;
+  FG_TRY(read_ctl(ws_dev, m, st, &c));
+  if (counters) {
+    counters->scaffold_evals += sat_evals;
+    counters->harvest_evals += c.counters[0];
+    counters->expansions += c.counters[1];
+    counters->prune_evals += c.counters[2];
+    counters->spilled_queries += c.counters[3];
+    counters->finalize_evals += c.fin[0] + c.fin[1];
+  }
+  if (timings) {
+    memset(timings, 0, sizeof(*timings));
+    auto ms = [&](int i, int j) {
+      float t = 0.f;
+      hipEventElapsedTime(&t, ev[i], ev[j]);
+      return t;
+    };
+    timings->scaffold_ms = ms(0, 1);
+    timings->nblocks = Be;
+    unsigned long long prev = 0;
+    for (uint32_t b = 0; b < Be; b++) {
+      int i0 = 2 + 3 * b;
+      float h = ms(i0, i0 + 1);
+      timings->block_harvest_ms[b] = h;
+      timings->harvest_ms += h;
+      timings->merge_ms += ms(i0 + 1, i0 + 2);
+      timings->block_evals[b] = blk_evals[b] - prev;
+      prev = blk_evals[b];
+    }
+    timings->finalize_ms = ms(1 + 3 * Be, 2 + 3 * Be);
+  }
+  cleanup();
+#undef FG_TRY
+  return status_error(c.status);
+}
+
+}  // extern "C"

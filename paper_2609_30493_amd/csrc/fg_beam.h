@@ -1,0 +1,395 @@
+// fg_beam.h -- the beam-search wave (harvest and query search) and the
+// occlusion prune, for gfx950.
+//
+// One wavefront serves one query at a time and takes queries from an atomic
+// work queue until the block is exhausted (persistent grid), so uneven beam
+// lengths do not idle the machine.
+//
+// Per query (Sec. 3): the beam is a sorted LDS array of at most ef keys
+// (distance, id) with an "expanded" flag per entry.  The roots are evaluated
+// first; then, repeatedly, the best unexpanded entry is expanded: its CSR row
+// is read 64 ids at a time, every id not yet visited is evaluated (groups of
+// L lanes gather one row each in 16-byte chunks), the new keys that can
+// still enter the beam are sorted across the wave and merged into the beam
+// by co-ranking.  The search ends when every beam entry is expanded.
+//
+// The visited set is exact: an LDS open-addressing table of HSLOTS ids; once
+// it is 3/4 full, further ids go to a per-wave bitset in device memory (and a
+// list of them, so the bitset can be cleared word by word afterwards).
+//
+// Harvest mode records the expanded entries and then prunes them (without
+// the query point itself): sorted by key, the next live candidate is kept,
+// and every later live candidate c with fl32(alpha * d(kept, c)) <= d(p, c)
+// dies; at most R are kept.
+#pragma once
+#include "fg_device.h"
+
+namespace fg {
+
+struct BeamArgs {
+  // data
+  const uint8_t* x;
+  int64_t stride;
+  int64_t n;
+  int Q;  // 16-byte chunks per row
+  // graph
+  const uint64_t* off;
+  const uint32_t* ids;
+  const uint32_t* roots;
+  int T;
+  int ef;
+  // harvest
+  int R;
+  float alpha;
+  int64_t b, B;  // points p = b + i * B
+  uint32_t* rows;
+  uint32_t* cnt;
+  // search
+  const uint8_t* queries;
+  int64_t qstride;
+  int k;
+  uint32_t* out_ids;
+  void* out_d;
+  uint32_t* out_evals;
+  // work
+  int64_t nitems;
+  unsigned long long* queue;
+  // scratch (per wave slot)
+  uint64_t* Ebuf;
+  int Ecap;
+  uint32_t* spill_bits;
+  int64_t spill_words;
+  uint32_t* spill_list;
+  int spill_cap;
+  unsigned long long* counters;  // evals, expansions, prune pairs, spilled
+  int* status;                   // bit 0: expanded-list overflow
+};
+
+template <int EFMAX, int HSLOTS>
+struct WaveLDS {
+  uint32_t htab[HSLOTS];  // visited ids; after the search, the prune's sort buffer
+  uint64_t bkeys[2][EFMAX];
+  uint8_t bflag[2][EFMAX];
+  uint64_t ckey[64];
+  uint32_t cid[64];
+  uint32_t alive[HSLOTS / 64];
+  uint32_t nspill;
+};
+
+__device__ __forceinline__ uint32_t hash_slot(uint32_t u) { return u * 0x9E3779B1u; }
+
+// Rows as the prune needs them.
+struct RowSet {
+  const uint8_t* x;
+  int64_t stride;
+  int Q;
+};
+
+// Distances from the register-resident row `a` (norm an) to the `cnt`
+// (<= 64) rows whose ids are in ids_lds; writes keys into keys_lds.
+template <int DK, int L, int NCH>
+__device__ __forceinline__ void batch_dists_rs(const RowSet& X, const Chunks<L, NCH>& a, uint32_t an,
+                                               const uint32_t* ids_lds, int cnt, uint64_t* keys_lds) {
+  constexpr int G = 64 / L;
+  constexpr int RB = (NCH >= 8) ? 1 : ((8 / NCH) < L ? (8 / NCH) : L);
+  const int lane = lane_id();
+  const int grp = lane / L, g = lane % L;
+  for (int r0 = 0; r0 < cnt; r0 += G * RB) {
+    Chunks<L, NCH> rc[RB];
+    uint32_t u[RB];
+#pragma unroll
+    for (int t = 0; t < RB; t++) {
+      int r = r0 + t * G + grp;
+      u[t] = ids_lds[r < cnt ? r : 0];
+      load_chunks<L, NCH>(rc[t], X.x + (size_t)u[t] * X.stride, X.Q, g);
+    }
+#pragma unroll
+    for (int t = 0; t < RB; t++) {
+      int r = r0 + t * G + grp;
+      uint32_t hi = group_dist<DK, L, NCH>(a, an, rc[t], X.Q, g);
+      if (r < cnt && g == 0) keys_lds[r] = make_key(hi, u[t]);
+    }
+  }
+  wave_sync();
+}
+
+// Ascending bitonic sort of M (a power of two >= 64) entries in LDS by one wave.
+template <typename T>
+__device__ __forceinline__ void wave_sort_lds(T* a, int M) {
+  const int lane = lane_id();
+  for (int kb = 2; kb <= M; kb <<= 1) {
+    for (int jb = kb >> 1; jb > 0; jb >>= 1) {
+      for (int i = lane; i < M; i += 64) {
+        int ixj = i ^ jb;
+        if (ixj > i) {
+          T a0 = a[i], a1 = a[ixj];
+          bool up = (i & kb) == 0;
+          if ((a0 > a1) == up) {
+            a[i] = a1;
+            a[ixj] = a0;
+          }
+        }
+      }
+      wave_sync();
+    }
+  }
+}
+
+// Greedy occlusion prune of the mc candidates sk[0..mc) (sorted by key; the
+// key's high word is d(p, c)).  alive holds >= mc bits of LDS scratch, cid /
+// ckey 64 entries each.  Writes the kept ids to out[0..kept) (lane 0) and
+// returns kept; *pe counts the pair distances evaluated (each later live
+// candidate against each kept one until it dies).
+template <int DK, int L, int NCH>
+__device__ int prune_wave(const RowSet& X, float alpha, int R, const uint64_t* sk, int mc,
+                          uint32_t* alive, uint32_t* cid, uint64_t* ckey, uint32_t* out,
+                          unsigned long long* pe) {
+  const int lane = lane_id();
+  const int g = lane % L;
+  for (int w = lane; w < (mc + 31) / 32; w += 64) {
+    int valid = mc - w * 32;
+    alive[w] = valid >= 32 ? 0xFFFFFFFFu : ((1u << valid) - 1u);
+  }
+  wave_sync();
+  int kept = 0, i = 0;
+  while (kept < R) {
+    int nxt = -1;
+    for (int base = i & ~63; base < mc; base += 64) {
+      int j = base + lane;
+      bool live = j >= i && j < mc && ((alive[j >> 5] >> (j & 31)) & 1u);
+      uint64_t m = ballot(live);
+      if (m) {
+        nxt = base + __ffsll((long long)m) - 1;
+        break;
+      }
+    }
+    if (nxt < 0) break;
+    i = nxt;
+    uint32_t kid = key_id(sk[i]);
+    if (lane == 0) out[kept] = kid;
+    kept++;
+    if (kept == R) break;
+    Chunks<L, NCH> kc;
+    load_chunks<L, NCH>(kc, X.x + (size_t)kid * X.stride, X.Q, g);
+    uint32_t kn = 0;
+    if constexpr (DK == U8L2) kn = group_sum_u32<L>(u8_selfdot<L, NCH>(kc));
+    for (int base = i + 1; base < mc; base += 64) {
+      int j = base + lane;
+      bool live = j < mc && ((alive[j >> 5] >> (j & 31)) & 1u);
+      uint64_t m = ballot(live);
+      int nl = popc64(m);
+      if (nl == 0) continue;
+      *pe += (unsigned long long)nl;
+      int pos = popc64(m & lanes_below());
+      if (live) cid[pos] = key_id(sk[j]);
+      wave_sync();
+      batch_dists_rs<DK, L, NCH>(X, kc, kn, cid, nl, ckey);
+      if (live) {
+        float dkc = hi_to_float<DK>(key_hi(ckey[pos]));
+        float dpc = hi_to_float<DK>(key_hi(sk[j]));
+        float scaled = alpha * dkc;
+        if (scaled <= dpc) atomicAnd(&alive[j >> 5], ~(1u << (j & 31)));
+      }
+      wave_sync();
+    }
+    i++;
+  }
+  return kept;
+}
+
+template <int DK, int L, int NCH, int EFMAX, int HSLOTS, bool SEARCH>
+__global__ void __launch_bounds__(64) k_beam(BeamArgs A) {
+  __shared__ WaveLDS<EFMAX, HSLOTS> S;
+  const int lane = lane_id();
+  const int g = lane % L;
+  const int64_t wslot = blockIdx.x;
+  uint32_t* bits = A.spill_bits + wslot * A.spill_words;
+  uint32_t* slist = A.spill_list + wslot * (int64_t)A.spill_cap;
+  uint64_t* E = A.Ebuf + wslot * (int64_t)A.Ecap;
+  constexpr uint32_t HMASK = HSLOTS - 1;
+  constexpr int HCAP = HSLOTS * 3 / 4 - 64;
+  const int ef = A.ef;
+  const RowSet X{A.x, A.stride, A.Q};
+
+  unsigned long long my_evals = 0, my_exp = 0, my_pe = 0, my_spilled = 0;
+
+  for (;;) {
+    unsigned long long item = 0;
+    if (lane == 0) item = atomicAdd(A.queue, 1ull);
+    item = __shfl(item, 0, 64);
+    if ((int64_t)item >= A.nitems) break;
+
+    const int64_t p = SEARCH ? (int64_t)item : A.b + (int64_t)item * A.B;
+    const uint8_t* qrow = SEARCH ? A.queries + (size_t)item * A.qstride : A.x + (size_t)p * A.stride;
+    Chunks<L, NCH> qc;
+    load_chunks<L, NCH>(qc, qrow, A.Q, g);
+    uint32_t qn = 0;
+    if constexpr (DK == U8L2) qn = group_sum_u32<L>(u8_selfdot<L, NCH>(qc));
+
+    for (int i = lane; i < HSLOTS; i += 64) S.htab[i] = FG_NONE;
+    if (lane == 0) S.nspill = 0;
+    wave_sync();
+    int bsize = 0, cur = 0, hcount = 0, En = 0;
+    bool spill = false, overflow = false;
+    unsigned long long evals = 0;
+
+    // Visit then evaluate a list of candidate ids (roots or a CSR row).
+    auto process = [&](const uint32_t* list, int64_t len) {
+      for (int64_t base = 0; base < len; base += 64) {
+        int64_t j = base + lane;
+        uint32_t u = j < len ? list[j] : FG_NONE;
+        bool isnew = false, in_lds = false;
+        if (u < (uint64_t)A.n) {  // ids outside [0, n) are ignored
+          uint32_t h = hash_slot(u) & HMASK;
+          bool found = false;
+          for (;;) {
+            uint32_t s = S.htab[h];
+            if (s == u) { found = true; break; }
+            if (s == FG_NONE) break;
+            h = (h + 1) & HMASK;
+          }
+          if (!found) {
+            if (!spill) {
+              for (;;) {
+                uint32_t old = atomicCAS(&S.htab[h], FG_NONE, u);
+                if (old == FG_NONE) { isnew = true; in_lds = true; break; }
+                if (old == u) break;
+                h = (h + 1) & HMASK;
+              }
+            } else {
+              uint32_t bit = 1u << (u & 31);
+              uint32_t old = atomicOr(&bits[u >> 5], bit);
+              if (!(old & bit)) {
+                isnew = true;
+                uint32_t idx = atomicAdd(&S.nspill, 1u);
+                if ((int)idx < A.spill_cap) slist[idx] = u;
+              }
+            }
+          }
+        }
+        hcount += popc64(ballot(in_lds));
+        if (hcount >= HCAP) spill = true;
+        uint64_t m = ballot(isnew);
+        int nnew = popc64(m);
+        evals += (unsigned long long)nnew;
+        if (nnew == 0) continue;
+        if (isnew) S.cid[popc64(m & lanes_below())] = u;
+        wave_sync();
+        batch_dists_rs<DK, L, NCH>(X, qc, qn, S.cid, nnew, S.ckey);
+        uint64_t ck = lane < nnew ? S.ckey[lane] : FG_KEY_NONE;
+        if (bsize == ef && ck >= S.bkeys[cur][ef - 1]) ck = FG_KEY_NONE;
+        ck = wave_sort64(ck);
+        int nc = popc64(ballot(ck != FG_KEY_NONE));
+        if (nc == 0) continue;
+        S.ckey[lane] = ck;
+        wave_sync();
+        // merge by co-ranking into the other buffer
+        const uint64_t* Bk = S.bkeys[cur];
+        const uint8_t* Bf = S.bflag[cur];
+        uint64_t* Nk = S.bkeys[cur ^ 1];
+        uint8_t* Nf = S.bflag[cur ^ 1];
+        if (lane < nc) {
+          int np = lane + lower_bound_lds<uint64_t>(Bk, bsize, ck);
+          if (np < ef) { Nk[np] = ck; Nf[np] = 0; }
+        }
+        for (int jb = lane; jb < bsize; jb += 64) {
+          uint64_t bk = Bk[jb];
+          int np = jb + lower_bound_lds<uint64_t>(S.ckey, nc, bk);
+          if (np < ef) { Nk[np] = bk; Nf[np] = Bf[jb]; }
+        }
+        bsize = bsize + nc < ef ? bsize + nc : ef;
+        cur ^= 1;
+        wave_sync();
+      }
+    };
+
+    process(A.roots, A.T);
+    for (;;) {
+      int first = -1;
+      for (int base = 0; base < bsize; base += 64) {
+        int j = base + lane;
+        uint64_t m = ballot(j < bsize && S.bflag[cur][j] == 0);
+        if (m) { first = base + __ffsll((long long)m) - 1; break; }
+      }
+      if (first < 0) break;
+      uint64_t key = S.bkeys[cur][first];
+      wave_sync();
+      if (lane == 0) S.bflag[cur][first] = 1;
+      if constexpr (!SEARCH) {
+        if (En >= A.Ecap) { overflow = true; break; }
+        if (lane == 0) E[En] = key;
+        En++;
+      }
+      my_exp++;
+      uint32_t v = key_id(key);
+      uint64_t s0 = A.off[v], s1 = A.off[v + 1];
+      wave_sync();
+      process(A.ids + s0, (int64_t)(s1 - s0));
+    }
+    my_evals += evals;
+
+    if constexpr (SEARCH) {
+      for (int i = lane; i < A.k; i += 64) {
+        uint64_t kk = i < bsize ? S.bkeys[cur][i] : FG_KEY_NONE;
+        A.out_ids[item * A.k + i] = i < bsize ? key_id(kk) : FG_NONE;
+        if constexpr (DK == U8L2)
+          reinterpret_cast<uint32_t*>(A.out_d)[item * A.k + i] = i < bsize ? key_hi(kk) : FG_NONE;
+        else
+          reinterpret_cast<float*>(A.out_d)[item * A.k + i] =
+              i < bsize ? ord_to_f32(key_hi(kk)) : __builtin_inff();
+      }
+      if (lane == 0 && A.out_evals) A.out_evals[item] = (uint32_t)evals;
+    } else {
+      uint32_t* out = A.rows + (size_t)p * A.R;
+      int kept = 0;
+      if (overflow) {
+        if (lane == 0) atomicOr(A.status, 1);
+      } else {
+        // Sort the expanded set (minus p) in LDS, then prune it.
+        uint64_t* sk = reinterpret_cast<uint64_t*>(S.htab);
+        int M = 64;
+        while (M < En) M <<= 1;
+        wave_sync();
+        for (int i = lane; i < M; i += 64) {
+          uint64_t kk = FG_KEY_NONE;
+          if (i < En) {
+            kk = E[i];
+            if (key_id(kk) == (uint32_t)p) kk = FG_KEY_NONE;
+          }
+          sk[i] = kk;
+        }
+        wave_sync();
+        wave_sort_lds<uint64_t>(sk, M);
+        int mc = 0;
+        for (int base = 0; base < M; base += 64) mc += popc64(ballot(sk[base + lane] != FG_KEY_NONE));
+        kept = prune_wave<DK, L, NCH>(X, A.alpha, A.R, sk, mc, S.alive, S.cid, S.ckey, out, &my_pe);
+      }
+      for (int t = kept + lane; t < A.R; t += 64) out[t] = FG_NONE;
+      if (lane == 0) A.cnt[p] = (uint32_t)kept;
+    }
+
+    // Return the spill bitset to all-zero for the next query.
+    if (spill) {
+      my_spilled++;
+      wave_sync();
+      uint32_t ns = S.nspill;
+      // Clear with atomics: the next query sets bits with atomics at L2, and
+      // plain stores are not ordered against them.
+      if ((int)ns <= A.spill_cap) {
+        for (uint32_t t = lane; t < ns; t += 64) atomicAnd(&bits[slist[t] >> 5], 0u);
+      } else {
+        for (int64_t t = lane; t < A.spill_words; t += 64) atomicAnd(&bits[t], 0u);
+      }
+      __threadfence();
+    }
+    wave_sync();
+  }
+  if (lane == 0) {
+    atomicAdd(&A.counters[0], my_evals);
+    atomicAdd(&A.counters[1], my_exp);
+    atomicAdd(&A.counters[2], my_pe);
+    atomicAdd(&A.counters[3], my_spilled);
+  }
+}
+
+}  // namespace fg

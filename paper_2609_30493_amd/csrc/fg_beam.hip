@@ -1,0 +1,82 @@
+// fg_beam.hip -- instantiation and dispatch of the beam kernels.
+//
+// A kernel is chosen by (distance kind, lanes per row L, chunks per lane NCH,
+// beam bound EFMAX): L lanes share one row so that a group reads 16*L
+// contiguous bytes per step; L*NCH must cover the row's 16-byte chunks.
+#include "fg_internal.h"
+
+namespace fg {
+
+namespace {
+
+template <int DK, int L, int NCH, int EFMAX, bool SEARCH>
+void* kernel_ptr() {
+  return reinterpret_cast<void*>(&k_beam<DK, L, NCH, EFMAX, kHashSlots, SEARCH>);
+}
+
+template <int DK, int L, int NCH, bool SEARCH>
+void* pick_ef(int ef) {
+  if constexpr (SEARCH) {
+    if (ef <= 128) return kernel_ptr<DK, L, NCH, 128, SEARCH>();
+    if (ef <= 512) return kernel_ptr<DK, L, NCH, 512, SEARCH>();
+  } else {
+    if (ef <= 64) return kernel_ptr<DK, L, NCH, 64, SEARCH>();
+    if (ef <= 128) return kernel_ptr<DK, L, NCH, 128, SEARCH>();
+    if (ef <= 256) return kernel_ptr<DK, L, NCH, 256, SEARCH>();
+  }
+  return nullptr;
+}
+
+template <bool SEARCH>
+void* pick(int dk, int Q, int ef) {
+  if (dk == U8L2) {
+    if (Q <= 8) return pick_ef<U8L2, 8, 1, SEARCH>(ef);
+    if (Q <= 16) return pick_ef<U8L2, 16, 1, SEARCH>(ef);
+    return nullptr;
+  }
+#define FG_F32_ROWS(DKV)                                         \
+  if (Q <= 8) return pick_ef<DKV, 8, 1, SEARCH>(ef);             \
+  if (Q <= 16) return pick_ef<DKV, 16, 1, SEARCH>(ef);           \
+  if (Q <= 32) return pick_ef<DKV, 16, 2, SEARCH>(ef);           \
+  if (Q <= 64) return pick_ef<DKV, 16, 4, SEARCH>(ef);           \
+  if (Q <= 256) return pick_ef<DKV, 16, 16, SEARCH>(ef);         \
+  return nullptr;
+  if (dk == F32L2) { FG_F32_ROWS(F32L2) }
+  if (dk == F32COS) { FG_F32_ROWS(F32COS) }
+#undef FG_F32_ROWS
+  return nullptr;
+}
+
+int num_cus() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (cus <= 0) cus = 256;
+  }
+  return cus;
+}
+
+}  // namespace
+
+int beam_grid(const Shape& s, int ef, bool search) {
+  void* k = search ? pick<true>(s.dk, s.Q, ef) : pick<false>(s.dk, s.Q, ef);
+  if (!k) return 0;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k), 64, 0) !=
+          hipSuccess ||
+      per_cu <= 0)
+    per_cu = 4;
+  int g = per_cu * num_cus();
+  return g < kMaxWaveSlots ? g : kMaxWaveSlots;
+}
+
+hipError_t launch_beam(const Shape& s, BeamArgs& a, bool search, int grid, hipStream_t st) {
+  void* k = search ? pick<true>(s.dk, s.Q, a.ef) : pick<false>(s.dk, s.Q, a.ef);
+  if (!k) return hipErrorInvalidValue;
+  void* args[] = {&a};
+  return hipLaunchKernel(reinterpret_cast<const void*>(k), dim3(grid), dim3(64), args, 0, st);
+}
+
+}  // namespace fg

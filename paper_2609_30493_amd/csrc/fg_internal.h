@@ -1,0 +1,76 @@
+// fg_internal.h -- host-side declarations shared by the library's sources.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/fgraft.h"
+#include "fg_beam.h"
+
+namespace fg {
+
+// Bounds of the beam kernels' on-chip structures.
+constexpr int kHashSlots = 4096;         // LDS visited table per wave
+constexpr int kEcap = kHashSlots / 2;    // expanded entries per search
+constexpr int kSpillCap = 8192;          // ids remembered for clearing the spill bitset
+constexpr int kMaxWaveSlots = 2048;      // persistent grid bound (wave slots)
+constexpr int kMaxEfHarvest = 256;
+constexpr int kMaxEfSearch = 512;
+
+void set_error(const std::string& msg);
+
+// Data shape as the kernels see it.
+struct Shape {
+  const uint8_t* x;
+  int64_t stride, n;
+  int d, dk, Q;  // dk = DistKind, Q = 16-byte chunks per row
+};
+bool make_shape(const fg_data* d, Shape* s);  // validates, sets error
+
+// Beam kernels (fg_beam.hip).  grid_for_beam() gives the persistent grid.
+int beam_grid(const Shape& s, int ef, bool search);
+hipError_t launch_beam(const Shape& s, BeamArgs& a, bool search, int grid, hipStream_t st);
+
+// Small utilities (fg_graph.hip).
+hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t st);
+hipError_t fill_u64(uint64_t* p, uint64_t v, int64_t count, hipStream_t st);
+// Exclusive scan of `count` uint32 values into uint64 offsets (count+1 entries).
+size_t scan_scratch_bytes(int64_t count);
+hipError_t exclusive_scan_u32_u64(const uint32_t* in, uint64_t* out, int64_t count,
+                                  void* scratch, hipStream_t st);
+
+// Edge lists from harvested rows (fg_graph.hip): points p = b + i*B.
+hipError_t edges_count(int64_t n, const uint32_t* rows, const uint32_t* cnt, int R, int64_t b, int64_t B,
+                       int64_t nitems, bool own, bool rev, uint32_t* deg, hipStream_t st);
+hipError_t edges_scatter(int64_t n, const uint32_t* rows, const uint32_t* cnt, int R, int64_t b, int64_t B,
+                         int64_t nitems, bool own, bool rev, const uint64_t* off, uint32_t* cursor,
+                         uint32_t* out, hipStream_t st);
+hipError_t merge_rows(int64_t n, const uint64_t* off, const uint32_t* ids, const uint64_t* addoff,
+                      const uint32_t* addbuf, uint32_t* tmp, uint32_t* newlen, int* status,
+                      hipStream_t st);
+hipError_t compact_rows(int64_t n, const uint64_t* off, const uint64_t* addoff, const uint32_t* tmp,
+                        const uint64_t* noff, uint32_t* out, hipStream_t st);
+hipError_t search_graph(int64_t n, int R, const uint32_t* nbrs, const uint32_t* cnt,
+                        const uint32_t* parent0, uint32_t* deg, uint64_t* off, uint32_t* out,
+                        void* scan_scratch, hipStream_t st);
+
+// Finalize rows (fg_finalize.hip): symmetrised candidates -> sorted / pruned.
+struct FinalizeArgs {
+  RowSet X;
+  int64_t n;
+  int R;
+  float alpha;
+  int reprune_all;
+  const uint32_t* rows;
+  const uint32_t* cnt;
+  const uint64_t* revoff;
+  const uint32_t* rev;
+  uint32_t* g_nbrs;
+  uint32_t* g_cnt;
+  unsigned long long* counters;  // [0] candidate distances, [1] prune pairs
+  int* status;                   // bit 2: candidate set above capacity
+};
+hipError_t launch_finalize(int dk, int Q, const FinalizeArgs& a, hipStream_t st);
+
+}  // namespace fg

@@ -1,0 +1,254 @@
+"""Thin Python binding of libfgraft.so (the C-ABI in include/fgraft.h).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+PyTorch supplies device memory and the stream.  If the library has not been
+built, every call raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfgraft.so")
+NONE = 0xFFFFFFFF
+
+FG_OK, FG_EINVAL, FG_ENOMEM, FG_EHIP, FG_ECAPACITY, FG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+F32, U8 = 0, 1
+L2SQ, COSINE = 0, 1
+
+
+class FgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"fgraft error {code}: {msg}")
+        self.code = code
+
+
+class fg_data(C.Structure):
+    _fields_ = [("x_dev", C.c_void_p), ("n", C.c_int64), ("d", C.c_int32),
+                ("dtype", C.c_int32), ("metric", C.c_int32), ("reserved", C.c_int32),
+                ("row_stride_bytes", C.c_int64)]
+
+
+class fg_params(C.Structure):
+    _fields_ = [("T", C.c_uint32), ("ef_h", C.c_uint32), ("R", C.c_uint32),
+                ("alpha", C.c_float), ("B", C.c_uint32), ("reprune_all", C.c_uint32),
+                ("reserved0", C.c_uint32), ("reserved1", C.c_uint32)]
+
+
+class fg_csr(C.Structure):
+    _fields_ = [("off_dev", C.c_void_p), ("ids_dev", C.c_void_p), ("n", C.c_int64),
+                ("nnz", C.c_uint64), ("cap", C.c_uint64)]
+
+
+class fg_graph(C.Structure):
+    _fields_ = [("nbrs_dev", C.c_void_p), ("cnt_dev", C.c_void_p),
+                ("spine_parent_dev", C.c_void_p), ("roots_dev", C.c_void_p),
+                ("n", C.c_int64), ("R", C.c_uint32), ("T", C.c_uint32)]
+
+
+class fg_counters(C.Structure):
+    _fields_ = [("scaffold_evals", C.c_uint64), ("harvest_evals", C.c_uint64),
+                ("prune_evals", C.c_uint64), ("expansions", C.c_uint64),
+                ("finalize_evals", C.c_uint64), ("spilled_queries", C.c_uint64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class fg_timings(C.Structure):
+    _fields_ = [("scaffold_ms", C.c_float), ("harvest_ms", C.c_float),
+                ("merge_ms", C.c_float), ("finalize_ms", C.c_float),
+                ("block_harvest_ms", C.c_float * 64), ("block_evals", C.c_uint64 * 64),
+                ("nblocks", C.c_uint32)]
+
+    def as_dict(self):
+        nb = int(self.nblocks)
+        return dict(scaffold_ms=self.scaffold_ms, harvest_ms=self.harvest_ms,
+                    merge_ms=self.merge_ms, finalize_ms=self.finalize_ms,
+                    block_harvest_ms=list(self.block_harvest_ms)[:nb],
+                    block_evals=[int(v) for v in list(self.block_evals)[:nb]])
+
+
+_lib = None
+P = C.c_void_p
+_SIGS = {
+    "fg_last_error": (C.c_char_p, []),
+    "fg_workspace_size": (C.c_size_t, [P, P]),
+    "fg_roots": (C.c_int, [C.c_uint64, C.c_int64, C.c_uint32, P]),
+    "fg_build_scaffold": (C.c_int, [P, P, C.c_uint32, P, P, P, C.c_size_t, P, P]),
+    "fg_harvest_block": (C.c_int, [P, P, P, P, C.c_uint32, P, P, P, C.c_size_t, P, P]),
+    "fg_merge_block": (C.c_int, [P, P, P, P, C.c_uint32, P, P, C.c_size_t, P]),
+    "fg_finalize": (C.c_int, [P, P, P, P, P, P, C.c_size_t, P, P]),
+    "fg_build_graph": (C.c_int, [P, C.c_uint64, P, P, P, C.c_size_t, P, P, P]),
+    "fg_search": (C.c_int, [P, P, P, C.c_int64, C.c_uint32, C.c_uint32, P, P, P, P,
+                            C.c_size_t, P]),
+    "fg_graph_hash": (C.c_int, [P, P, P]),
+}
+
+
+def lib():
+    """Load libfgraft.so; raise if it is missing (never fall back)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name, None)
+            if f is not None:
+                f.restype = res
+                f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    L = lib()
+    return [n for n in _SIGS if getattr(L, n, None) is not None]
+
+
+def _check(rc: int):
+    if rc != FG_OK:
+        raise FgError(rc, lib().fg_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+# The C structures hold raw device pointers; each one keeps a reference to
+# the tensors it points into (attribute `_keep`), so a temporary passed to a
+# constructor stays allocated as long as the structure does.
+
+def make_data(x: torch.Tensor, metric: str = "l2") -> fg_data:
+    if x.dim() != 2 or not x.is_cuda or x.stride(1) != 1:
+        raise ValueError("x must be a 2-D row-major device tensor")
+    if x.dtype == torch.float32:
+        dt = F32
+    elif x.dtype == torch.uint8:
+        dt = U8
+    else:
+        raise TypeError(x.dtype)
+    s = fg_data(x.data_ptr(), x.shape[0], x.shape[1], dt,
+                COSINE if metric == "cosine" else L2SQ, 0,
+                x.stride(0) * x.element_size())
+    s._keep = (x,)
+    return s
+
+
+def make_params(T, ef_h, R, alpha=1.2, B=1, reprune_all=0) -> fg_params:
+    return fg_params(T, ef_h, R, alpha, B, reprune_all, 0, 0)
+
+
+def workspace_size(data: fg_data, params: fg_params) -> int:
+    return int(lib().fg_workspace_size(C.byref(data), C.byref(params)))
+
+
+def alloc_workspace(data: fg_data, params: fg_params, device="cuda") -> torch.Tensor:
+    nb = workspace_size(data, params)
+    return torch.empty(nb + 256, dtype=torch.uint8, device=device)
+
+
+def _ws(ws: torch.Tensor):
+    base = ws.data_ptr()
+    pad = (-base) % 256
+    return C.c_void_p(base + pad), ws.numel() - pad
+
+
+def roots(seed: int, n: int, T: int):
+    import numpy as np
+    r = np.zeros(T, np.uint32)
+    _check(lib().fg_roots(seed, n, T, r.ctypes.data_as(C.c_void_p)))
+    return r
+
+
+def csr(off: torch.Tensor, ids: torch.Tensor, nnz: int | None = None) -> fg_csr:
+    for t in (off, ids):
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("CSR arrays must be contiguous device tensors")
+    n = off.numel() - 1
+    s = fg_csr(off.data_ptr(), ids.data_ptr(), n,
+               int(nnz if nnz is not None else ids.numel()), ids.numel())
+    s._keep = (off, ids)
+    return s
+
+
+def harvest_block(data: fg_data, Sb: fg_csr, roots_dev: torch.Tensor, params: fg_params,
+                  b: int, rows: torch.Tensor, cnt: torch.Tensor, ws: torch.Tensor,
+                  stream=None, counters: bool = True):
+    c = fg_counters()
+    wp, wn = _ws(ws)
+    _check(lib().fg_harvest_block(C.byref(data), C.byref(Sb), _ptr(roots_dev),
+                                  C.byref(params), b, _ptr(rows), _ptr(cnt), wp, wn,
+                                  _stream(stream), C.byref(c) if counters else None))
+    return c.as_dict()
+
+
+def build_scaffold(data: fg_data, roots_dev: torch.Tensor, T: int, S0: fg_csr,
+                   tree_parent: torch.Tensor | None, ws: torch.Tensor, stream=None):
+    c = fg_counters()
+    wp, wn = _ws(ws)
+    _check(lib().fg_build_scaffold(C.byref(data), _ptr(roots_dev), T, C.byref(S0),
+                                   _ptr(tree_parent), wp, wn, _stream(stream), C.byref(c)))
+    return c.as_dict()
+
+
+def merge_block(Sb: fg_csr, rows: torch.Tensor, cnt: torch.Tensor, params: fg_params, b: int,
+                Sb1: fg_csr, ws: torch.Tensor, stream=None):
+    wp, wn = _ws(ws)
+    _check(lib().fg_merge_block(C.byref(Sb), _ptr(rows), _ptr(cnt), C.byref(params), b,
+                                C.byref(Sb1), wp, wn, _stream(stream)))
+    return int(Sb1.nnz)
+
+
+def make_graph(nbrs, cnt, spine_parent, roots_dev, T: int) -> fg_graph:
+    for t in (nbrs, cnt, spine_parent, roots_dev):
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("graph arrays must be contiguous device tensors")
+    if cnt.numel() != nbrs.shape[0] or spine_parent.numel() != nbrs.shape[0] or roots_dev.numel() < T:
+        raise ValueError("graph array sizes do not match")
+    s = fg_graph(nbrs.data_ptr(), cnt.data_ptr(), spine_parent.data_ptr(),
+                 roots_dev.data_ptr(), nbrs.shape[0], nbrs.shape[1], T)
+    s._keep = (nbrs, cnt, spine_parent, roots_dev)
+    return s
+
+
+def finalize(data: fg_data, rows, cnt, params: fg_params, graph: fg_graph, ws, stream=None):
+    c = fg_counters()
+    wp, wn = _ws(ws)
+    _check(lib().fg_finalize(C.byref(data), _ptr(rows), _ptr(cnt), C.byref(params),
+                             C.byref(graph), wp, wn, _stream(stream), C.byref(c)))
+    return c.as_dict()
+
+
+def build_graph(data: fg_data, seed: int, params: fg_params, graph: fg_graph, ws,
+                stream=None, timings: bool = False):
+    c = fg_counters()
+    t = fg_timings()
+    wp, wn = _ws(ws)
+    _check(lib().fg_build_graph(C.byref(data), seed, C.byref(params), C.byref(graph), wp, wn,
+                                _stream(stream), C.byref(c), C.byref(t) if timings else None))
+    return c.as_dict(), (t.as_dict() if timings else None)
+
+
+def search(data: fg_data, graph: fg_graph, queries: torch.Tensor, k: int, L: int,
+           out_ids, out_d, out_evals, ws, stream=None):
+    wp, wn = _ws(ws)
+    _check(lib().fg_search(C.byref(data), C.byref(graph), _ptr(queries), queries.shape[0], k,
+                           L, _ptr(out_ids), _ptr(out_d), _ptr(out_evals), wp, wn,
+                           _stream(stream)))
+
+
+def graph_hash(graph: fg_graph, stream=None) -> int:
+    h = C.c_uint64(0)
+    _check(lib().fg_graph_hash(C.byref(graph), _stream(stream), C.byref(h)))
+    return int(h.value)
