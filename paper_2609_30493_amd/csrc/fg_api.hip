@@ -67,6 +67,8 @@ uint32_t b_eff(const fg_params* p) { return p->B > 1 ? p->B : 1; }
 struct WsMap {
   size_t ctl, bits, slist, ebuf;            // beam kernels
   size_t deg, cursor, newlen, aoff, noff, zoff, addbuf, tmp, scan;  // edge lists / merges
+  size_t keys, keys2, uni, big, ksegs, ktiles;  // rows too large for on-chip sorting
+  size_t ktile_cap;
   size_t sgoff, sgids;                      // search graph
   size_t off[2], ids[2], rows, cnt, tparent, roots;  // the whole build
   size_t sat;
@@ -105,6 +107,13 @@ WsMap ws_map(int64_t n, const fg_params* p) {
   m.addbuf = take(m.add_cap * 4);
   m.tmp = take(m.tmp_cap * 4);
   m.scan = take(scan_scratch_bytes((int64_t)un + 1));
+  m.keys = take(m.add_cap * 8);
+  m.keys2 = take(m.add_cap * 8);
+  m.uni = take(m.add_cap * 4);
+  m.big = take(un * 4);
+  m.ksegs = take(un * sizeof(KSeg));
+  m.ktile_cap = m.add_cap / kSegTilePositions + un + 64;
+  m.ktiles = take(m.ktile_cap * sizeof(KTile));
   m.sgoff = take((un + 1) * 8);
   m.sgids = take((R * un + 2 * un + 1) * 4);
   for (int i = 0; i < 2; i++) {
@@ -126,8 +135,8 @@ struct Ctl {
   unsigned long long queue;
   unsigned long long counters[4];    // beam: evals, expansions, prune pairs, spilled
   unsigned long long fin[2];         // finalize: candidate distances, prune pairs
-  unsigned long long pad;
-  int status;                        // 1 expanded-set, 2 merge-row, 4 finalize-row overflow
+  uint32_t nbig, pad32;              // rows sent to the big-row paths
+  int status;                        // 1 expanded-set overflow
 };
 
 hipError_t g_last_hip = hipSuccess;
@@ -203,6 +212,26 @@ fg_status read_ctl(void* ws, const WsMap& m, hipStream_t st, Ctl* out) {
   return FG_OK;
 }
 
+// Per-row union of sorted old rows with unsorted additions (see merge_rows);
+// rows with too many additions for one wave's LDS take the global path.
+fg_status merge_rows_all(int64_t n, const uint64_t* off0, const uint32_t* ids0, const uint64_t* aoff,
+                         const uint32_t* addbuf, uint32_t* tmp, uint32_t* newlen, void* ws, const WsMap& m,
+                         hipStream_t st) {
+  Ctl* ctl = reinterpret_cast<Ctl*>(at(ws, m.ctl));
+  uint32_t* big = reinterpret_cast<uint32_t*>(at(ws, m.big));
+  FG_HIP(fill_u32(&ctl->nbig, 0, 1, st));
+  FG_HIP(merge_rows(n, off0, ids0, aoff, addbuf, tmp, newlen, big, &ctl->nbig, st));
+  uint32_t nbig = 0;
+  FG_HIP(hipMemcpyAsync(&nbig, &ctl->nbig, 4, hipMemcpyDeviceToHost, st));
+  FG_HIP(hipStreamSynchronize(st));
+  FG_HIP(merge_big_rows(big, nbig, off0, ids0, aoff, addbuf, tmp, newlen,
+                        reinterpret_cast<KSeg*>(at(ws, m.ksegs)), reinterpret_cast<KTile*>(at(ws, m.ktiles)),
+                        m.ktile_cap, reinterpret_cast<uint64_t*>(at(ws, m.keys)),
+                        reinterpret_cast<uint64_t*>(at(ws, m.keys2)), reinterpret_cast<uint32_t*>(at(ws, m.uni)),
+                        st));
+  return FG_OK;
+}
+
 // S_{b+1} = S_b u rows of block b (both directions), sorted and deduplicated
 // per row.  Leaves the new offsets in off1 (off1[n] = nnz) and the ids in
 // ids1; the caller guarantees the capacity.
@@ -223,7 +252,8 @@ fg_status merge_launch(int64_t n, const uint64_t* off0, const uint32_t* ids0, co
   FG_HIP(exclusive_scan_u32_u64(deg, aoff, n, scan, st));
   FG_HIP(fill_u32(cursor, 0, n, st));
   FG_HIP(edges_scatter(n, rows, cnt, R, b, Be, nitems, true, true, aoff, cursor, addbuf, st));
-  FG_HIP(merge_rows(n, off0, ids0, aoff, addbuf, tmp, newlen, &ctl->status, st));
+  fg_status r = merge_rows_all(n, off0, ids0, aoff, addbuf, tmp, newlen, ws, m, st);
+  if (r) return r;
   FG_HIP(exclusive_scan_u32_u64(newlen, off1, n, scan, st));
   FG_HIP(compact_rows(n, off0, aoff, tmp, off1, ids1, st));
   return FG_OK;
@@ -244,7 +274,8 @@ fg_status scaffold_csr_launch(int64_t n, uint32_t T, const uint32_t* tparent, ui
   Ctl* ctl = reinterpret_cast<Ctl*>(at(ws, m.ctl));
   FG_HIP(tree_edges_csr(n, T, tparent, deg, aoff, cursor, addbuf, st, scan));
   FG_HIP(fill_u64(zoff, 0, n + 1, st));
-  FG_HIP(merge_rows(n, zoff, addbuf, aoff, addbuf, tmp, newlen, &ctl->status, st));
+  fg_status r = merge_rows_all(n, zoff, addbuf, aoff, addbuf, tmp, newlen, ws, m, st);
+  if (r) return r;
   FG_HIP(exclusive_scan_u32_u64(newlen, off, n, scan, st));
   FG_HIP(compact_rows(n, zoff, aoff, tmp, off, ids, st));
   return FG_OK;
@@ -279,14 +310,17 @@ fg_status finalize_launch(const Shape& s, const uint32_t* rows, const uint32_t* 
   f.g_cnt = g_cnt;
   f.counters = ctl->fin;
   f.status = &ctl->status;
-  FG_HIP(launch_finalize(s.dk, s.Q, f, st));
+  f.big = reinterpret_cast<uint32_t*>(at(ws, m.big));
+  f.nbig = &ctl->nbig;
+  FG_HIP(fill_u32(&ctl->nbig, 0, 1, st));
+  FinalizeBig fb{reinterpret_cast<KSeg*>(at(ws, m.ksegs)), reinterpret_cast<KTile*>(at(ws, m.ktiles)), m.ktile_cap,
+                 reinterpret_cast<uint64_t*>(at(ws, m.keys)), reinterpret_cast<uint64_t*>(at(ws, m.keys2))};
+  FG_HIP(launch_finalize(s.dk, s.Q, f, fb, st));
   return FG_OK;
 }
 
 fg_status status_error(int status) {
   if (status & 1) return set_error("a search expanded more vertices than its capacity"), FG_ECAPACITY;
-  if (status & 2) return set_error("a row gained more than 2048 edges in one merge"), FG_ECAPACITY;
-  if (status & 4) return set_error("a point has more than 2048 finalize candidates"), FG_ECAPACITY;
   if (status & 8) return set_error("the tree builder's segment list overflowed"), FG_ECAPACITY;
   return FG_OK;
 }

@@ -2,13 +2,16 @@
 // with its reverse edges, deduplicated, sorted by (d(p,.), id) and, when it
 // holds more than R candidates (or always with reprune_all), occlusion-pruned
 // to at most R.  One wave per point.
+#include <vector>
+
 #include "fg_internal.h"
 
 namespace fg {
 
 namespace {
 
-constexpr int kFinCap = 2048;  // candidates per point held on chip
+constexpr int kFinCap = 2048;      // candidates per point held on chip
+constexpr int kFinKeptMax = 1024;  // R bound of the big-row path
 
 template <int DK, int L, int NCH>
 __global__ void __launch_bounds__(64) k_finalize(FinalizeArgs A) {
@@ -26,12 +29,8 @@ __global__ void __launch_bounds__(64) k_finalize(FinalizeArgs A) {
     const uint64_t r0 = A.revoff[p];
     const int rc = (int)(A.revoff[p + 1] - r0);
     const int m0 = c + rc;
-    if (m0 > kFinCap) {
-      if (lane == 0) {
-        atomicOr(A.status, 4);
-        A.g_cnt[p] = 0;
-      }
-      for (int t = lane; t < A.R; t += 64) out[t] = FG_NONE;
+    if (m0 > kFinCap) {  // finished by the big-row path
+      if (lane == 0) A.big[atomicAdd(A.nbig, 1u)] = (uint32_t)p;
       continue;
     }
     int M = 64;
@@ -90,27 +89,164 @@ __global__ void __launch_bounds__(64) k_finalize(FinalizeArgs A) {
   }
 }
 
+// ---------------------------------------------------------------- big rows
+// A point with more than kFinCap candidates: its candidate keys live in a
+// device segment [revoff[p] + p*R, + c + rc), sorted by segsort_u64, and are
+// pruned in a stream of chunks of 64: each chunk is first tested against the
+// rows kept so far (in order, stopping at the first that occludes), then
+// resolved within itself.  Once R are kept, later chunks are still tested
+// against the first R-1 kept rows, so the pair count equals that of the
+// greedy prune run over the whole sorted list.
+__global__ void k_fin_big_segs(FinalizeArgs A, KSeg* segs) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < *A.nbig; i += gridDim.x * blockDim.x) {
+    uint32_t p = A.big[i];
+    uint32_t c = min(A.cnt[p], (uint32_t)A.R);
+    uint64_t rc = A.revoff[p + 1] - A.revoff[p];
+    segs[i] = KSeg{A.revoff[p] + (uint64_t)p * A.R, (uint32_t)(c + rc), 0};
+  }
+}
+
 template <int DK, int L, int NCH>
-hipError_t go(const FinalizeArgs& a, hipStream_t st) {
+__global__ void __launch_bounds__(64) k_fin_big_keys(FinalizeArgs A, const KSeg* segs, uint64_t* keys) {
+  __shared__ uint32_t cid[64];
+  __shared__ uint64_t ckey[64];
+  const int lane = lane_id(), g = lane % L;
+  const uint32_t p = A.big[blockIdx.x];
+  const KSeg sg = segs[blockIdx.x];
+  const uint32_t c = min(A.cnt[p], (uint32_t)A.R);
+  const uint64_t r0 = A.revoff[p];
+  Chunks<L, NCH> qc;
+  load_chunks<L, NCH>(qc, A.X.x + (size_t)p * A.X.stride, A.X.Q, g);
+  uint32_t qn = 0;
+  if constexpr (DK == U8L2) qn = group_sum_u32<L>(u8_selfdot<L, NCH>(qc));
+  for (uint32_t base = 0; base < sg.len; base += 64) {
+    uint32_t j = base + lane;
+    uint32_t v = FG_NONE;
+    if (j < sg.len) v = j < c ? A.rows[(uint64_t)p * A.R + j] : A.rev[r0 + (j - c)];
+    bool ok = v < (uint64_t)A.n;
+    uint64_t m = ballot(ok);
+    int cnt = popc64(m);
+    if (ok) cid[popc64(m & lanes_below())] = v;
+    wave_sync();
+    if (cnt) batch_dists_rs<DK, L, NCH>(A.X, qc, qn, cid, cnt, ckey);
+    // keep each candidate at its own slot; invalid ids sort last
+    uint64_t kk = FG_KEY_NONE;
+    if (ok) kk = ckey[popc64(m & lanes_below())];
+    if (j < sg.len) keys[sg.start + j] = kk;
+    wave_sync();
+  }
+}
+
+template <int DK, int L, int NCH>
+__global__ void __launch_bounds__(64) k_fin_big_prune(FinalizeArgs A, const KSeg* segs, const uint64_t* keys) {
+  __shared__ uint32_t kept[kFinKeptMax];
+  __shared__ uint64_t sk[64];
+  __shared__ uint32_t alive[2];
+  __shared__ uint32_t cid[64];
+  __shared__ uint64_t ckey[64];
+  const int lane = lane_id(), g = lane % L;
+  const uint32_t p = A.big[blockIdx.x];
+  const KSeg sg = segs[blockIdx.x];
+  const int R = A.R;
+  unsigned long long ev = 0, pe = 0;
+  int kc = 0;
+  bool full = false;
+  uint64_t carry = FG_KEY_NONE;
+  for (uint32_t base = 0; base < sg.len; base += 64) {
+    uint32_t j = base + lane;
+    uint64_t x = j < sg.len ? keys[sg.start + j] : FG_KEY_NONE;
+    uint64_t prev = shfl64(x, lane > 0 ? lane - 1 : 0);
+    if (lane == 0) prev = carry;
+    carry = shfl64(x, 63);
+    bool uniq = x != FG_KEY_NONE && x != prev;
+    uint64_t um = ballot(uniq);
+    int k = popc64(um);
+    ev += (unsigned long long)k;
+    if (k == 0) continue;
+    const int myslot = popc64(um & lanes_below());
+    // filter against the kept rows (after R are kept, only the first R-1)
+    const int nk = full ? R - 1 : kc;
+    bool live = uniq;
+    for (int i = 0; i < nk; i++) {
+      uint64_t lm = ballot(live);
+      int nl = popc64(lm);
+      if (nl == 0) break;
+      if (live) cid[popc64(lm & lanes_below())] = key_id(x);
+      wave_sync();
+      Chunks<L, NCH> kcn;
+      load_chunks<L, NCH>(kcn, A.X.x + (size_t)kept[i] * A.X.stride, A.X.Q, g);
+      uint32_t kn = 0;
+      if constexpr (DK == U8L2) kn = group_sum_u32<L>(u8_selfdot<L, NCH>(kcn));
+      batch_dists_rs<DK, L, NCH>(A.X, kcn, kn, cid, nl, ckey);
+      pe += (unsigned long long)nl;
+      if (live) {
+        float dkc = hi_to_float<DK>(key_hi(ckey[popc64(lm & lanes_below())]));
+        float dpc = hi_to_float<DK>(key_hi(x));
+        if (A.alpha * dkc <= dpc) live = false;
+      }
+      wave_sync();
+    }
+    if (full) continue;
+    // resolve the chunk's survivors among themselves
+    uint64_t lm = ballot(live);
+    int nl = popc64(lm);
+    if (nl) {
+      if (live) sk[popc64(lm & lanes_below())] = x;
+      wave_sync();
+      int add = prune_wave<DK, L, NCH>(A.X, A.alpha, R - kc, sk, nl, alive, cid, ckey, kept + kc, &pe);
+      kc += add;
+      if (kc == R) full = true;
+    }
+    wave_sync();
+    (void)myslot;
+  }
+  uint32_t* out = A.g_nbrs + (uint64_t)p * R;
+  for (int t = lane; t < R; t += 64) out[t] = t < kc ? kept[t] : FG_NONE;
+  if (lane == 0) {
+    A.g_cnt[p] = (uint32_t)kc;
+    atomicAdd(&A.counters[0], ev);
+    atomicAdd(&A.counters[1], pe);
+  }
+}
+
+template <int DK, int L, int NCH>
+hipError_t go(const FinalizeArgs& a, const FinalizeBig& big, hipStream_t st) {
   int grid = (int)(a.n < 65536 ? a.n : 65536);
   k_finalize<DK, L, NCH><<<grid, 64, 0, st>>>(a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  uint32_t nbig = 0;
+  e = hipMemcpyAsync(&nbig, a.nbig, 4, hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess || nbig == 0) return e;
+  k_fin_big_segs<<<(nbig + 255) / 256, 256, 0, st>>>(a, big.segs);
+  std::vector<KSeg> hsegs(nbig);
+  e = hipMemcpyAsync(hsegs.data(), big.segs, nbig * sizeof(KSeg), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  k_fin_big_keys<DK, L, NCH><<<nbig, 64, 0, st>>>(a, big.segs, big.keys);
+  e = segsort_u64(big.keys, big.keys2, big.segs, hsegs, big.tiles, big.tile_cap, st);
+  if (e != hipSuccess) return e;
+  k_fin_big_prune<DK, L, NCH><<<nbig, 64, 0, st>>>(a, big.segs, big.keys);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_finalize(int dk, int Q, const FinalizeArgs& a, hipStream_t st) {
+hipError_t launch_finalize(int dk, int Q, const FinalizeArgs& a, const FinalizeBig& big, hipStream_t st) {
   if (dk == U8L2) {
-    if (Q <= 8) return go<U8L2, 8, 1>(a, st);
-    if (Q <= 16) return go<U8L2, 16, 1>(a, st);
+    if (Q <= 8) return go<U8L2, 8, 1>(a, big, st);
+    if (Q <= 16) return go<U8L2, 16, 1>(a, big, st);
     return hipErrorInvalidValue;
   }
 #define FG_F32_ROWS(DKV)                              \
-  if (Q <= 8) return go<DKV, 8, 1>(a, st);            \
-  if (Q <= 16) return go<DKV, 16, 1>(a, st);          \
-  if (Q <= 32) return go<DKV, 16, 2>(a, st);          \
-  if (Q <= 64) return go<DKV, 16, 4>(a, st);          \
-  if (Q <= 256) return go<DKV, 16, 16>(a, st);        \
+  if (Q <= 8) return go<DKV, 8, 1>(a, big, st);            \
+  if (Q <= 16) return go<DKV, 16, 1>(a, big, st);          \
+  if (Q <= 32) return go<DKV, 16, 2>(a, big, st);          \
+  if (Q <= 64) return go<DKV, 16, 4>(a, big, st);          \
+  if (Q <= 256) return go<DKV, 16, 16>(a, big, st);        \
   return hipErrorInvalidValue;
   if (dk == F32L2) { FG_F32_ROWS(F32L2) }
   if (dk == F32COS) { FG_F32_ROWS(F32COS) }

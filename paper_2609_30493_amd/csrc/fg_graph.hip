@@ -1,4 +1,6 @@
 // fg_graph.hip -- fills and prefix scans used by the graph-building steps.
+#include <vector>
+
 #include "fg_internal.h"
 
 namespace fg {
@@ -140,7 +142,8 @@ constexpr int kMergeAddMax = 2048;
 
 __global__ void __launch_bounds__(64) k_merge_rows(int64_t n, const uint64_t* off, const uint32_t* ids,
                                                    const uint64_t* addoff, const uint32_t* addbuf,
-                                                   uint32_t* tmp, uint32_t* newlen, int* status) {
+                                                   uint32_t* tmp, uint32_t* newlen, uint32_t* big,
+                                                   uint32_t* nbig) {
   __shared__ uint32_t buf[kMergeAddMax];
   __shared__ uint32_t uni[kMergeAddMax];
   const int lane = lane_id();
@@ -155,9 +158,10 @@ __global__ void __launch_bounds__(64) k_merge_rows(int64_t n, const uint64_t* of
       if (lane == 0) newlen[v] = (uint32_t)o;
       continue;
     }
-    if (a > kMergeAddMax) {
+    if (a > kMergeAddMax) {  // handled by the big-row path
       if (lane == 0) {
-        atomicOr(status, 2);
+        uint32_t at = atomicAdd(nbig, 1u);
+        big[at] = (uint32_t)v;
         newlen[v] = 0;
       }
       continue;
@@ -260,6 +264,144 @@ __global__ void k_search_fill(int64_t n, int R, const uint32_t* nbrs, const uint
   }
 }
 
+// ------------------------------------------------------------------ segmented sort
+// Ascending sort of each segment [start, start + len) of a key array, for
+// segments of any length: every tile of kSegTile keys is sorted by one wave
+// in LDS, then runs of width 2^k * kSegTile are merged pairwise (each key's
+// output slot is its rank in its own run plus its rank in the partner run).
+constexpr int kSegTile = 256;
+
+__global__ void __launch_bounds__(64) k_seg_tile_sort(const KSeg* segs, const KTile* tiles, uint64_t* keys) {
+  __shared__ uint64_t sk[kSegTile];
+  const int lane = lane_id();
+  const KTile tl = tiles[blockIdx.x];
+  const KSeg sg = segs[tl.seg];
+  const uint32_t cnt = min((uint32_t)kSegTile, sg.len - tl.off);
+  for (int i = lane; i < kSegTile; i += 64) sk[i] = i < (int)cnt ? keys[sg.start + tl.off + i] : FG_KEY_NONE;
+  wave_sync();
+  wave_sort_lds<uint64_t>(sk, kSegTile);
+  for (int i = lane; i < (int)cnt; i += 64) keys[sg.start + tl.off + i] = sk[i];
+}
+
+__global__ void __launch_bounds__(64) k_seg_merge_pass(const KSeg* segs, const KTile* tiles, const uint64_t* src,
+                                                       uint64_t* dst, uint32_t w) {
+  const int lane = lane_id();
+  const KTile tl = tiles[blockIdx.x];
+  const KSeg sg = segs[tl.seg];
+  const uint64_t* s = src + sg.start;
+  uint64_t* d = dst + sg.start;
+  const uint32_t hi = min(sg.len, tl.off + kSegTile);
+  for (uint32_t j = tl.off + lane; j < hi; j += 64) {
+    uint64_t k = s[j];
+    uint32_t r = j / w;
+    uint32_t pb = (r & ~1u) * w;
+    uint32_t lo_o, hi_o, mine;
+    if ((r & 1u) == 0) {
+      mine = j - pb;
+      lo_o = min(pb + w, sg.len);
+      hi_o = min(pb + 2 * w, sg.len);
+    } else {
+      mine = j - pb - w;
+      lo_o = pb;
+      hi_o = pb + w;
+    }
+    // stable: the left run's keys go before equal keys of the right run
+    const bool left = (r & 1u) == 0;
+    uint32_t a = lo_o, b = hi_o;
+    while (a < b) {
+      uint32_t m = (a + b) >> 1;
+      if (left ? (s[m] < k) : (s[m] <= k)) a = m + 1;
+      else b = m;
+    }
+    d[pb + mine + (a - lo_o)] = k;
+  }
+}
+
+__global__ void __launch_bounds__(64) k_seg_copy(const KSeg* segs, const KTile* tiles, const uint64_t* src,
+                                                 uint64_t* dst) {
+  const KTile tl = tiles[blockIdx.x];
+  const KSeg sg = segs[tl.seg];
+  const uint32_t hi = min(sg.len, tl.off + kSegTile);
+  for (uint32_t j = tl.off + lane_id(); j < hi; j += 64) dst[sg.start + j] = src[sg.start + j];
+}
+
+// ------------------------------------------------------------------ big merge rows
+// Segment descriptors of the rows listed in `big` (their additions).
+__global__ void k_big_segs(const uint32_t* big, uint32_t nbig, const uint64_t* addoff, KSeg* segs) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nbig; i += gridDim.x * blockDim.x) {
+    uint32_t v = big[i];
+    segs[i] = KSeg{addoff[v], (uint32_t)(addoff[v + 1] - addoff[v]), 0};
+  }
+}
+
+__global__ void __launch_bounds__(64) k_big_widen(const KSeg* segs, const KTile* tiles, const uint32_t* addbuf,
+                                                  uint64_t* keys) {
+  const KTile tl = tiles[blockIdx.x];
+  const KSeg sg = segs[tl.seg];
+  const uint32_t hi = min(sg.len, tl.off + kSegTile);
+  for (uint32_t j = tl.off + lane_id(); j < hi; j += 64) keys[sg.start + j] = addbuf[sg.start + j];
+}
+
+// One wave per big row: the sorted additions (keys, id in the low word)
+// deduplicated and stripped of ids already in the old row, compacted into
+// uni (same offsets), then merged with the old row into tmp.
+__global__ void __launch_bounds__(64) k_merge_big(const uint32_t* big, const KSeg* segs, const uint64_t* off,
+                                                  const uint32_t* ids, const uint64_t* addoff, const uint64_t* keys,
+                                                  uint32_t* uni, uint32_t* tmp, uint32_t* newlen) {
+  const int lane = lane_id();
+  const uint32_t v = big[blockIdx.x];
+  const KSeg sg = segs[blockIdx.x];
+  const uint64_t o0 = off[v];
+  const int64_t o = (int64_t)(off[v + 1] - o0);
+  uint32_t* u_out = uni + sg.start;
+  auto in_old = [&](uint32_t x) {
+    int64_t lo = 0, hi = o;
+    while (lo < hi) {
+      int64_t mid = (lo + hi) >> 1;
+      if (ids[o0 + mid] < x) lo = mid + 1;
+      else hi = mid;
+    }
+    return lo < o && ids[o0 + lo] == x;
+  };
+  uint32_t u = 0;
+  uint32_t carry = FG_NONE;
+  for (uint32_t base = 0; base < sg.len; base += 64) {
+    uint32_t j = base + lane;
+    uint32_t x = j < sg.len ? (uint32_t)keys[sg.start + j] : FG_NONE;
+    uint32_t prev = __shfl(x, lane > 0 ? lane - 1 : 0, 64);
+    if (lane == 0) prev = carry;
+    carry = __shfl(x, 63, 64);
+    bool keep = x != FG_NONE && x != prev && !in_old(x);
+    uint64_t m = ballot(keep);
+    if (keep) u_out[u + popc64(m & lanes_below())] = x;
+    u += popc64(m);
+  }
+  wave_sync();
+  __threadfence();
+  uint32_t* dst = tmp + o0 + addoff[v];
+  for (int64_t j = lane; j < o; j += 64) {
+    uint32_t x = ids[o0 + j];
+    uint32_t lo = 0, hi = u;
+    while (lo < hi) {
+      uint32_t mid = (lo + hi) >> 1;
+      if (u_out[mid] < x) lo = mid + 1;
+      else hi = mid;
+    }
+    dst[j + lo] = x;
+  }
+  for (uint32_t i = lane; i < u; i += 64) {
+    uint32_t x = u_out[i];
+    int64_t lo = 0, hi = o;
+    while (lo < hi) {
+      int64_t mid = (lo + hi) >> 1;
+      if (ids[o0 + mid] < x) lo = mid + 1;
+      else hi = mid;
+    }
+    dst[i + lo] = x;
+  }
+  if (lane == 0) newlen[v] = (uint32_t)(o + u);
+}
+
 }  // namespace
 
 hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t st) {
@@ -307,10 +449,65 @@ hipError_t edges_scatter(int64_t n, const uint32_t* rows, const uint32_t* cnt, i
 }
 
 hipError_t merge_rows(int64_t n, const uint64_t* off, const uint32_t* ids, const uint64_t* addoff,
-                      const uint32_t* addbuf, uint32_t* tmp, uint32_t* newlen, int* status,
+                      const uint32_t* addbuf, uint32_t* tmp, uint32_t* newlen, uint32_t* big, uint32_t* nbig,
                       hipStream_t st) {
   int grid = (int)(n < 65536 ? n : 65536);
-  k_merge_rows<<<grid, 64, 0, st>>>(n, off, ids, addoff, addbuf, tmp, newlen, status);
+  k_merge_rows<<<grid, 64, 0, st>>>(n, off, ids, addoff, addbuf, tmp, newlen, big, nbig);
+  return hipGetLastError();
+}
+
+hipError_t segsort_u64(uint64_t* keys, uint64_t* keys2, const KSeg* dsegs, const std::vector<KSeg>& hsegs,
+                       KTile* dtiles, size_t tile_cap, hipStream_t st) {
+  std::vector<KTile> tiles;
+  uint32_t maxlen = 0;
+  for (uint32_t i = 0; i < hsegs.size(); i++) {
+    for (uint32_t o = 0; o < hsegs[i].len; o += kSegTile) tiles.push_back(KTile{i, o});
+    maxlen = maxlen > hsegs[i].len ? maxlen : hsegs[i].len;
+  }
+  if (tiles.empty()) return hipSuccess;
+  if (tiles.size() > tile_cap) return hipErrorOutOfMemory;
+  hipError_t e = hipMemcpyAsync(dtiles, tiles.data(), tiles.size() * sizeof(KTile), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  // the host vector must outlive the copy
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  const unsigned nt = (unsigned)tiles.size();
+  k_seg_tile_sort<<<nt, 64, 0, st>>>(dsegs, dtiles, keys);
+  uint64_t* src = keys;
+  uint64_t* dst = keys2;
+  for (uint32_t w = kSegTile; w < maxlen; w *= 2) {
+    k_seg_merge_pass<<<nt, 64, 0, st>>>(dsegs, dtiles, src, dst, w);
+    uint64_t* t = src;
+    src = dst;
+    dst = t;
+  }
+  if (src != keys) k_seg_copy<<<nt, 64, 0, st>>>(dsegs, dtiles, src, keys);
+  return hipGetLastError();
+}
+
+hipError_t merge_big_rows(const uint32_t* big, uint32_t nbig, const uint64_t* off, const uint32_t* ids,
+                          const uint64_t* addoff, const uint32_t* addbuf, uint32_t* tmp, uint32_t* newlen,
+                          KSeg* dsegs, KTile* dtiles, size_t tile_cap, uint64_t* keys, uint64_t* keys2,
+                          uint32_t* uni, hipStream_t st) {
+  if (nbig == 0) return hipSuccess;
+  k_big_segs<<<blocks_for(nbig, 256), 256, 0, st>>>(big, nbig, addoff, dsegs);
+  std::vector<KSeg> hsegs(nbig);
+  hipError_t e = hipMemcpyAsync(hsegs.data(), dsegs, nbig * sizeof(KSeg), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  std::vector<KTile> tiles;
+  for (uint32_t i = 0; i < nbig; i++)
+    for (uint32_t o = 0; o < hsegs[i].len; o += kSegTile) tiles.push_back(KTile{i, o});
+  if (tiles.size() > tile_cap) return hipErrorOutOfMemory;
+  e = hipMemcpyAsync(dtiles, tiles.data(), tiles.size() * sizeof(KTile), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  k_big_widen<<<(unsigned)tiles.size(), 64, 0, st>>>(dsegs, dtiles, addbuf, keys);
+  e = segsort_u64(keys, keys2, dsegs, hsegs, dtiles, tile_cap, st);
+  if (e != hipSuccess) return e;
+  k_merge_big<<<nbig, 64, 0, st>>>(big, dsegs, off, ids, addoff, keys, uni, tmp, newlen);
   return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/fgraft.h"
 #include "fg_beam.h"
@@ -46,9 +47,26 @@ hipError_t edges_count(int64_t n, const uint32_t* rows, const uint32_t* cnt, int
 hipError_t edges_scatter(int64_t n, const uint32_t* rows, const uint32_t* cnt, int R, int64_t b, int64_t B,
                          int64_t nitems, bool own, bool rev, const uint64_t* off, uint32_t* cursor,
                          uint32_t* out, hipStream_t st);
+// Rows whose additions exceed the on-chip bound are listed in big[] (count
+// in *nbig) and finished by merge_big_rows().
 hipError_t merge_rows(int64_t n, const uint64_t* off, const uint32_t* ids, const uint64_t* addoff,
-                      const uint32_t* addbuf, uint32_t* tmp, uint32_t* newlen, int* status,
+                      const uint32_t* addbuf, uint32_t* tmp, uint32_t* newlen, uint32_t* big, uint32_t* nbig,
                       hipStream_t st);
+struct KSeg {
+  uint64_t start;
+  uint32_t len, pad;
+};
+struct KTile {
+  uint32_t seg, off;
+};
+constexpr int kSegTilePositions = 256;
+// Sort each segment of keys (keys2: same-size scratch).  hsegs mirrors dsegs.
+hipError_t segsort_u64(uint64_t* keys, uint64_t* keys2, const KSeg* dsegs, const std::vector<KSeg>& hsegs,
+                       KTile* dtiles, size_t tile_cap, hipStream_t st);
+hipError_t merge_big_rows(const uint32_t* big, uint32_t nbig, const uint64_t* off, const uint32_t* ids,
+                          const uint64_t* addoff, const uint32_t* addbuf, uint32_t* tmp, uint32_t* newlen,
+                          KSeg* dsegs, KTile* dtiles, size_t tile_cap, uint64_t* keys, uint64_t* keys2,
+                          uint32_t* uni, hipStream_t st);
 hipError_t compact_rows(int64_t n, const uint64_t* off, const uint64_t* addoff, const uint32_t* tmp,
                         const uint64_t* noff, uint32_t* out, hipStream_t st);
 hipError_t search_graph(int64_t n, int R, const uint32_t* nbrs, const uint32_t* cnt,
@@ -69,8 +87,17 @@ struct FinalizeArgs {
   uint32_t* g_nbrs;
   uint32_t* g_cnt;
   unsigned long long* counters;  // [0] candidate distances, [1] prune pairs
-  int* status;                   // bit 2: candidate set above capacity
+  int* status;
+  uint32_t* big;   // points whose candidates exceed the on-chip bound
+  uint32_t* nbig;  // their count (device, zero on entry)
 };
-hipError_t launch_finalize(int dk, int Q, const FinalizeArgs& a, hipStream_t st);
+struct FinalizeBig {
+  KSeg* segs;
+  KTile* tiles;
+  size_t tile_cap;
+  uint64_t* keys;
+  uint64_t* keys2;
+};
+hipError_t launch_finalize(int dk, int Q, const FinalizeArgs& a, const FinalizeBig& big, hipStream_t st);
 
 }  // namespace fg

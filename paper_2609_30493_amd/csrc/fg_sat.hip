@@ -94,10 +94,12 @@ __global__ void __launch_bounds__(64) k_sat_merge_pass(SatArgs A, const uint64_t
       other_lo = pb;
       other_hi = pb + w;
     }
+    // stable: the left run's keys go before equal keys of the right run
+    const bool left = (r & 1u) == 0;
     uint32_t a = other_lo, b = other_hi;
     while (a < b) {
       uint32_t m = (a + b) >> 1;
-      if (s[m] < k) a = m + 1;
+      if (left ? (s[m] < k) : (s[m] <= k)) a = m + 1;
       else b = m;
     }
     d[pb + mine + (a - other_lo)] = k;

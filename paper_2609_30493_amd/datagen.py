@@ -189,3 +189,26 @@ def small_u8(n: int, d: int, seed: int, hi: int = 4) -> np.ndarray:
     """Tiny-range integer data: many exact distance ties."""
     rng = np.random.default_rng(seed)
     return rng.integers(0, hi, size=(n, d)).astype(np.uint8)
+
+
+def hub_u8(n: int, d: int, seed: int, radius: float = 50.0) -> np.ndarray:
+    """Row 0 at the centre (128, ..., 128), every other row on a noisy shell
+    of the given radius around it: the centre is every point's nearest
+    neighbour, so its in-degree in a k-NN-like graph approaches n."""
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal((n, d))
+    g /= np.linalg.norm(g, axis=1, keepdims=True)
+    r = radius * (1.0 + 0.1 * rng.random((n, 1)))
+    v = np.clip(np.rint(128.0 + r * g), 0, 255)
+    v[0] = 128.0
+    return v.astype(np.uint8)
+
+
+def hub_f32(n: int, d: int, seed: int) -> np.ndarray:
+    """Float version of hub_u8: centre at the origin, a noisy unit shell."""
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal((n, d))
+    g /= np.linalg.norm(g, axis=1, keepdims=True)
+    v = g * (1.0 + 0.1 * rng.random((n, 1)))
+    v[0] = 0.0
+    return v.astype(np.float32)

@@ -27,6 +27,10 @@ DATASETS = {
     "identical-50": lambda: (np.ones((50, 4), np.float32), "l2"),
     "single-1": lambda: (np.zeros((1, 16), np.uint8), "l2"),
     "pair-2": lambda: (np.array([[1] * 16, [3] * 16], np.uint8), "l2"),
+    # a centre point that is every point's nearest neighbour: rows of
+    # thousands of entries in S0, in the merges and in finalize
+    "hub-u8-6000": lambda: (gen.hub_u8(6000, 128, 1), "l2"),
+    "hub-f32-6000": lambda: (gen.hub_f32(6000, 32, 2), "l2"),
 }
 
 
@@ -39,7 +43,8 @@ def _data(name):
 @pytest.mark.parametrize("name,T", [("u8-d16-3000", 4), ("u8-ties-2000", 3), ("u8-cfg2-9000", 8),
                                     ("f32-d32-2500", 4), ("f32-cos-d100-1500", 8),
                                     ("f32-d960-600", 2), ("collinear-400", 3),
-                                    ("duplicates-900", 4), ("identical-50", 2), ("pair-2", 2)])
+                                    ("duplicates-900", 4), ("identical-50", 2), ("pair-2", 2),
+                                    ("hub-u8-6000", 4)])
 def test_scaffold_matches_oracle(fgo, name, T):
     F = _lib()
     say(f"scaffold parity {name} T={T}")
@@ -63,7 +68,8 @@ def test_scaffold_matches_oracle(fgo, name, T):
 
 
 @pytest.mark.parametrize("name,T,R,B,b", [("u8-d16-3000", 4, 16, 4, 2), ("f32-d32-2500", 4, 24, 3, 0),
-                                          ("u8-cfg2-9000", 8, 32, 8, 6)])
+                                          ("u8-cfg2-9000", 8, 32, 8, 6), ("hub-u8-6000", 4, 16, 2, 0),
+                                          ("hub-f32-6000", 4, 16, 2, 1)])
 def test_merge_matches_oracle(fgo, name, T, R, B, b):
     F = _lib()
     say(f"merge parity {name} R={R} B={B} b={b}")
@@ -94,7 +100,8 @@ def test_merge_matches_oracle(fgo, name, T, R, B, b):
 
 
 @pytest.mark.parametrize("name,T,R,B,reprune", [("u8-d16-3000", 3, 8, 2, 0), ("f32-d32-2500", 4, 24, 1, 0),
-                                                ("f32-cos-d100-1500", 4, 12, 2, 1)])
+                                                ("f32-cos-d100-1500", 4, 12, 2, 1), ("hub-u8-6000", 4, 16, 2, 0),
+                                                ("hub-f32-6000", 4, 16, 2, 1), ("hub-u8-6000", 4, 1, 2, 0)])
 def test_finalize_matches_oracle(fgo, name, T, R, B, reprune):
     F = _lib()
     say(f"finalize parity {name} R={R} reprune_all={reprune}")
@@ -136,6 +143,8 @@ BUILDS = [
     ("identical-50", 2, 64, 8, 1.2, 64),
     ("single-1", 1, 4, 4, 1.2, 2),
     ("pair-2", 2, 4, 4, 1.2, 1),
+    ("hub-u8-6000", 4, 32, 16, 1.2, 2),
+    ("hub-f32-6000", 4, 32, 16, 1.2, 3),
 ]
 
 
