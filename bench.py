@@ -27,6 +27,26 @@ from paper_2609_30493_amd import datagen as gen  # noqa: E402
 from paper_2609_30493_amd import fgraft as F  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_beam_harvest_u8_1M_pmc.md")
+
+
+def measured_traffic():
+    """Bytes per harvest launch from the committed counter summary, or None
+    when the beam kernel's source changed since the counters were taken."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(PMC_SUMMARY):
+            if ":" in line and not line.startswith(("|", "#", "`")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        src = b"".join(open(os.path.join(ROOT, "paper_2609_30493_amd", "csrc", f), "rb").read()
+                       for f in ("fg_beam.h", "fg_device.h"))
+        if hashlib.sha256(src).hexdigest()[:16] != kv.get("kernel_source_sha256_16"):
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def log(msg: str) -> None:
@@ -89,6 +109,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=100_000)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the timed steps, copy 1 GiB device to device (a plain copy "
+                         "kernel of known size, to scale profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -155,10 +178,21 @@ def main():
         "counters": c0,
         "graph_hash": f"{ghash:#018x}",
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_beam (harvest)", "launches": launches,
                      "bytes_per_eval": row_bytes},
     }
+    out["block_harvest_ms"] = [round(v, 3) for v in t0_["block_harvest_ms"]]
+    out["block_evals"] = t0_["block_evals"]
+    if args.calib_copy:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        a.fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = a.numel()
+        del a, b
     if not args.no_recall:
         qd = torch.from_numpy(gen.workload_queries(w)).cuda()
         true_d = ground_truth_u8(xd, qd, 10).cpu().numpy().astype(np.float64)
