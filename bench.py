@@ -109,6 +109,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=100_000)
+    ap.add_argument("--table", type=int, default=0, choices=(0, 2048, 4096),
+                    help="on-chip visited-table slots per search (0 = library default)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed steps, copy 1 GiB device to device (a plain copy "
                          "kernel of known size, to scale profiler byte counters)")
@@ -124,7 +126,7 @@ def main():
     x = gen.workload_data(w, n)
     xd = torch.from_numpy(x).cuda()
     data = F.make_data(xd)
-    params = F.make_params(w.T, w.ef_h, w.R, w.alpha, w.B)
+    params = F.make_params(w.T, w.ef_h, w.R, w.alpha, w.B, beam_table_slots=args.table)
     ws = F.alloc_workspace(data, params)
     log(f"[bench] workspace {ws.numel() / 2**30:.2f} GiB")
 
@@ -171,7 +173,8 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": w.name, "n": n, "d": w.d, "T": w.T, "B": w.B, "ef_h": w.ef_h,
-                   "R": w.R, "alpha": w.alpha, "seed": w.build_seed},
+                   "R": w.R, "alpha": w.alpha, "seed": w.build_seed,
+                   "beam_table_slots": args.table or (2048 if w.ef_h <= 128 else 4096)},
         "build_s": wall / args.steps,
         "phase_ms": {k: t0_[k] for k in ("scaffold_ms", "harvest_ms", "merge_ms", "finalize_ms")},
         "harvest_evals_per_build": c0["harvest_evals"],

@@ -72,7 +72,11 @@ typedef struct {
 
 /* Build parameters (Sec. 3).  B = 0 and B = 1 both mean one frozen block
  * (frozen Graft).  reprune_all = 0 re-prunes in finalize only the rows whose
- * symmetrised candidate set exceeds R; 1 re-prunes every row. */
+ * symmetrised candidate set exceeds R; 1 re-prunes every row.
+ * beam_table_slots is a tuning knob that never changes the graph: the size
+ * of each harvest search's on-chip visited table, 2048 or 4096 (0 = 2048
+ * when ef_h <= 128, else 4096; ef_h > 128 always uses 4096).  A search
+ * whose expanded set exceeds half the table size fails with FG_ECAPACITY. */
 typedef struct {
   uint32_t T;
   uint32_t ef_h;
@@ -80,7 +84,7 @@ typedef struct {
   float alpha;
   uint32_t B;
   uint32_t reprune_all;
-  uint32_t reserved0;
+  uint32_t beam_table_slots;
   uint32_t reserved1;
 } fg_params;
 

@@ -57,10 +57,20 @@ bool check_params(const fg_params* p, int64_t n, bool need_ef = true) {
     return set_error("need 1 <= ef_h <= 256"), false;
   if (p->R < 1 || p->R > 1024) return set_error("need 1 <= R <= 1024"), false;
   if (!isfinite(p->alpha) || p->alpha < 1.0f) return set_error("alpha must be finite and >= 1"), false;
+  if (p->beam_table_slots != 0 && p->beam_table_slots != 2048 && p->beam_table_slots != 4096)
+    return set_error("beam_table_slots must be 0, 2048 or 4096"), false;
   return true;
 }
 
 uint32_t b_eff(const fg_params* p) { return p->B > 1 ? p->B : 1; }
+
+// Visited-table size for the harvest: the caller's choice, else 2048 slots
+// when ef_h <= 128 (more searches resident per compute unit; measured faster
+// on the 1M uint8 build) and 4096 otherwise.
+int table_request(const fg_params* p) {
+  if (p->beam_table_slots == 2048 || p->beam_table_slots == 4096) return (int)p->beam_table_slots;
+  return p->ef_h <= 128 ? 2048 : 4096;
+}
 
 // ---------------------------------------------------------------- workspace
 // One layout serves every entry point for a given (n, T, R, B).
@@ -169,7 +179,8 @@ fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* id
   Ctl* ctl = reinterpret_cast<Ctl*>(at(ws, m.ctl));
   FG_HIP(fill_u64(reinterpret_cast<uint64_t*>(&ctl->queue), 0, 1, st));
   if (nitems == 0) return FG_OK;
-  int grid = beam_grid(s, (int)P->ef_h, false);
+  const int hslots = beam_table_slots((int)P->ef_h, false, table_request(P));
+  int grid = beam_grid(s, (int)P->ef_h, false, hslots);
   if (grid <= 0) return set_error("no beam kernel for this row size / ef_h"), FG_EUNSUPPORTED;
   BeamArgs a{};
   a.x = s.x;
@@ -190,14 +201,14 @@ fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* id
   a.nitems = nitems;
   a.queue = &ctl->queue;
   a.Ebuf = reinterpret_cast<uint64_t*>(at(ws, m.ebuf));
-  a.Ecap = kEcap;
+  a.Ecap = hslots / 2;  // the expanded set is sorted in the visited table's space
   a.spill_bits = reinterpret_cast<uint32_t*>(at(ws, m.bits));
   a.spill_words = m.spill_words;
   a.spill_list = reinterpret_cast<uint32_t*>(at(ws, m.slist));
   a.spill_cap = kSpillCap;
   a.counters = ctl->counters;
   a.status = &ctl->status;
-  FG_HIP(launch_beam(s, a, false, grid, st));
+  FG_HIP(launch_beam(s, a, false, grid, hslots, st));
   return FG_OK;
 }
 
@@ -530,7 +541,7 @@ fg_status fg_search(const fg_data* data, const fg_graph* graph, const void* quer
   FG_HIP(search_graph(s.n, (int)graph->R, graph->nbrs_dev, graph->cnt_dev, graph->spine_parent_dev,
                       reinterpret_cast<uint32_t*>(at(ws_dev, m.deg)), sgoff, sgids, at(ws_dev, m.scan), st));
   FG_HIP(fill_u32(reinterpret_cast<uint32_t*>(at(ws_dev, m.bits)), 0, (int64_t)kMaxWaveSlots * m.spill_words, st));
-  int grid = beam_grid(s, (int)L, true);
+  int grid = beam_grid(s, (int)L, true, 4096);
   if (grid <= 0) return set_error("no search kernel for this row size / L"), FG_EUNSUPPORTED;
   Ctl* ctl = reinterpret_cast<Ctl*>(at(ws_dev, m.ctl));
   BeamArgs a{};
@@ -559,7 +570,7 @@ fg_status fg_search(const fg_data* data, const fg_graph* graph, const void* quer
   a.spill_cap = kSpillCap;
   a.counters = ctl->counters;
   a.status = &ctl->status;
-  FG_HIP(launch_beam(s, a, true, grid, st));
+  FG_HIP(launch_beam(s, a, true, grid, 4096, st));
   return FG_OK;
 }
 

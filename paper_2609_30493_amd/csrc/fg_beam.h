@@ -26,6 +26,27 @@
 
 namespace fg {
 
+// Phase timers for a profiling build (-DFG_PROFILE): shader-clock cycles
+// spent by lane 0 of every wave in each phase of the beam loop, summed over
+// the grid into fg_prof_cycles[].  Absent from normal builds.
+#ifdef FG_PROFILE
+extern __device__ unsigned long long fg_prof_cycles[16];
+#define FG_T0() uint64_t fg_t0_ = __builtin_amdgcn_s_memtime()
+#define FG_TICK(slot)                                        \
+  do {                                                       \
+    uint64_t fg_t1_ = __builtin_amdgcn_s_memtime();          \
+    prof[slot] += fg_t1_ - fg_t0_;                           \
+    fg_t0_ = fg_t1_;                                         \
+  } while (0)
+#else
+#define FG_T0() \
+  do {          \
+  } while (0)
+#define FG_TICK(slot) \
+  do {                \
+  } while (0)
+#endif
+
 struct BeamArgs {
   // data
   const uint8_t* x;
@@ -72,11 +93,17 @@ struct WaveLDS {
   uint8_t bflag[2][EFMAX];
   uint64_t ckey[64];
   uint32_t cid[64];
+  uint32_t sid[256];   // new ids of one super-chunk of neighbours
+  uint64_t skey[256];  // their keys
   uint32_t alive[HSLOTS / 64];
   uint32_t nspill;
 };
 
-__device__ __forceinline__ uint32_t hash_slot(uint32_t u) { return u * 0x9E3779B1u; }
+// Fibonacci hashing: the top log2(HSLOTS) bits of u * 2^32 / golden ratio.
+template <int HSLOTS>
+__device__ __forceinline__ uint32_t hash_slot(uint32_t u) {
+  return (u * 0x9E3779B1u) >> (32 - __builtin_ctz((unsigned)HSLOTS));
+}
 
 // Rows as the prune needs them.
 struct RowSet {
@@ -87,11 +114,17 @@ struct RowSet {
 
 // Distances from the register-resident row `a` (norm an) to the `cnt`
 // (<= 64) rows whose ids are in ids_lds; writes keys into keys_lds.
-template <int DK, int L, int NCH>
+template <int NCH, int L>
+constexpr int default_rb() {
+  return (NCH >= 8) ? 1 : ((8 / NCH) < L ? (8 / NCH) : L);
+}
+
+// RB rows per lane group are loaded before any is reduced, so a wave keeps
+// (64 / L) * RB row gathers in flight.
+template <int DK, int L, int NCH, int RB = default_rb<NCH, L>()>
 __device__ __forceinline__ void batch_dists_rs(const RowSet& X, const Chunks<L, NCH>& a, uint32_t an,
                                                const uint32_t* ids_lds, int cnt, uint64_t* keys_lds) {
   constexpr int G = 64 / L;
-  constexpr int RB = (NCH >= 8) ? 1 : ((8 / NCH) < L ? (8 / NCH) : L);
   const int lane = lane_id();
   const int grp = lane / L, g = lane % L;
   for (int r0 = 0; r0 < cnt; r0 += G * RB) {
@@ -207,11 +240,16 @@ __global__ void __launch_bounds__(64) k_beam(BeamArgs A) {
   uint32_t* slist = A.spill_list + wslot * (int64_t)A.spill_cap;
   uint64_t* E = A.Ebuf + wslot * (int64_t)A.Ecap;
   constexpr uint32_t HMASK = HSLOTS - 1;
-  constexpr int HCAP = HSLOTS * 3 / 4 - 64;
+  constexpr int HCAP = HSLOTS / 2 - 64;  // load <= 1/2; checked after every 64 insertions
+  constexpr int kRB = (NCH >= 16) ? 1 : 16 / NCH;
   const int ef = A.ef;
   const RowSet X{A.x, A.stride, A.Q};
 
   unsigned long long my_evals = 0, my_exp = 0, my_pe = 0, my_spilled = 0;
+#ifdef FG_PROFILE
+  unsigned long long prof[16] = {};
+#endif
+  FG_T0();
 
   for (;;) {
     unsigned long long item = 0;
@@ -233,76 +271,111 @@ __global__ void __launch_bounds__(64) k_beam(BeamArgs A) {
     bool spill = false, overflow = false;
     unsigned long long evals = 0;
 
-    // Visit then evaluate a list of candidate ids (roots or a CSR row).
+    // Visit then evaluate a list of candidate ids (roots or a CSR row), 256
+    // ids per step: the id loads, the visited checks (and the device bitset
+    // atomics once the LDS table is full) of all 256 are issued before any
+    // result is waited for; the new ids' rows are gathered 64*RB/L at a time;
+    // keys that can still enter the beam are merged 64 at a time.
     auto process = [&](const uint32_t* list, int64_t len) {
-      for (int64_t base = 0; base < len; base += 64) {
-        int64_t j = base + lane;
-        uint32_t u = j < len ? list[j] : FG_NONE;
-        bool isnew = false, in_lds = false;
-        if (u < (uint64_t)A.n) {  // ids outside [0, n) are ignored
-          uint32_t h = hash_slot(u) & HMASK;
-          bool found = false;
-          for (;;) {
-            uint32_t s = S.htab[h];
-            if (s == u) { found = true; break; }
-            if (s == FG_NONE) break;
-            h = (h + 1) & HMASK;
-          }
-          if (!found) {
-            if (!spill) {
-              for (;;) {
-                uint32_t old = atomicCAS(&S.htab[h], FG_NONE, u);
-                if (old == FG_NONE) { isnew = true; in_lds = true; break; }
-                if (old == u) break;
-                h = (h + 1) & HMASK;
-              }
+      for (int64_t base = 0; base < len; base += 256) {
+        uint32_t u[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+          int64_t j = base + k * 64 + lane;
+          u[k] = j < len ? list[j] : FG_NONE;
+        }
+        bool isnew[4], need[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+          isnew[k] = false;
+          need[k] = false;
+          bool in_lds = false;
+          if (u[k] < (uint64_t)A.n) {  // ids outside [0, n) are ignored
+            if (spill) {
+              need[k] = true;  // the bitset holds every visited id
             } else {
-              uint32_t bit = 1u << (u & 31);
-              uint32_t old = atomicOr(&bits[u >> 5], bit);
-              if (!(old & bit)) {
-                isnew = true;
-                uint32_t idx = atomicAdd(&S.nspill, 1u);
-                if ((int)idx < A.spill_cap) slist[idx] = u;
+              uint32_t h = hash_slot<HSLOTS>(u[k]);
+              for (;;) {
+                uint32_t old = atomicCAS(&S.htab[h], FG_NONE, u[k]);
+                if (old == FG_NONE) { isnew[k] = true; in_lds = true; break; }
+                if (old == u[k]) break;
+                h = (h + 1) & HMASK;
               }
             }
           }
+          hcount += popc64(ballot(in_lds));
+          if (!spill && hcount >= HCAP) {
+            // Table full: move its ids into the device bitset (listed for
+            // clearing), then use the bitset alone for this search.
+            wave_sync();
+            for (int i = lane; i < HSLOTS; i += 64) {
+              uint32_t v = S.htab[i];
+              if (v != FG_NONE) {
+                atomicOr(&bits[v >> 5], 1u << (v & 31));
+                uint32_t idx = atomicAdd(&S.nspill, 1u);
+                if ((int)idx < A.spill_cap) slist[idx] = v;
+              }
+            }
+            spill = true;
+          }
+          wave_sync();
         }
-        hcount += popc64(ballot(in_lds));
-        if (hcount >= HCAP) spill = true;
-        uint64_t m = ballot(isnew);
-        int nnew = popc64(m);
+        FG_TICK(0);
+        uint32_t old[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+          if (need[k]) old[k] = atomicOr(&bits[u[k] >> 5], 1u << (u[k] & 31));
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+          if (need[k] && !(old[k] & (1u << (u[k] & 31)))) {
+            isnew[k] = true;
+            uint32_t idx = atomicAdd(&S.nspill, 1u);
+            if ((int)idx < A.spill_cap) slist[idx] = u[k];
+          }
+        FG_TICK(1);
+        int nnew = 0;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+          uint64_t m = ballot(isnew[k]);
+          if (isnew[k]) S.sid[nnew + popc64(m & lanes_below())] = u[k];
+          nnew += popc64(m);
+        }
         evals += (unsigned long long)nnew;
         if (nnew == 0) continue;
-        if (isnew) S.cid[popc64(m & lanes_below())] = u;
         wave_sync();
-        batch_dists_rs<DK, L, NCH>(X, qc, qn, S.cid, nnew, S.ckey);
-        uint64_t ck = lane < nnew ? S.ckey[lane] : FG_KEY_NONE;
-        if (bsize == ef && ck >= S.bkeys[cur][ef - 1]) ck = FG_KEY_NONE;
-        ck = wave_sort64(ck);
-        int nc = popc64(ballot(ck != FG_KEY_NONE));
-        if (nc == 0) continue;
-        S.ckey[lane] = ck;
-        wave_sync();
-        // merge by co-ranking into the other buffer
-        const uint64_t* Bk = S.bkeys[cur];
-        const uint8_t* Bf = S.bflag[cur];
-        uint64_t* Nk = S.bkeys[cur ^ 1];
-        uint8_t* Nf = S.bflag[cur ^ 1];
-        if (lane < nc) {
-          int np = lane + lower_bound_lds<uint64_t>(Bk, bsize, ck);
-          if (np < ef) { Nk[np] = ck; Nf[np] = 0; }
+        batch_dists_rs<DK, L, NCH, kRB>(X, qc, qn, S.sid, nnew, S.skey);
+        FG_TICK(2);
+        for (int c0 = 0; c0 < nnew; c0 += 64) {
+          uint64_t ck = c0 + lane < nnew ? S.skey[c0 + lane] : FG_KEY_NONE;
+          if (bsize == ef && ck >= S.bkeys[cur][ef - 1]) ck = FG_KEY_NONE;
+          if (!ballot(ck != FG_KEY_NONE)) continue;
+          ck = wave_sort64(ck);
+          int nc = popc64(ballot(ck != FG_KEY_NONE));
+          S.ckey[lane] = ck;
+          wave_sync();
+          // merge by co-ranking into the other buffer
+          const uint64_t* Bk = S.bkeys[cur];
+          const uint8_t* Bf = S.bflag[cur];
+          uint64_t* Nk = S.bkeys[cur ^ 1];
+          uint8_t* Nf = S.bflag[cur ^ 1];
+          if (lane < nc) {
+            int np = lane + lower_bound_lds<uint64_t>(Bk, bsize, ck);
+            if (np < ef) { Nk[np] = ck; Nf[np] = 0; }
+          }
+          for (int jb = lane; jb < bsize; jb += 64) {
+            uint64_t bk = Bk[jb];
+            int np = jb + lower_bound_lds<uint64_t>(S.ckey, nc, bk);
+            if (np < ef) { Nk[np] = bk; Nf[np] = Bf[jb]; }
+          }
+          bsize = bsize + nc < ef ? bsize + nc : ef;
+          cur ^= 1;
+          wave_sync();
         }
-        for (int jb = lane; jb < bsize; jb += 64) {
-          uint64_t bk = Bk[jb];
-          int np = jb + lower_bound_lds<uint64_t>(S.ckey, nc, bk);
-          if (np < ef) { Nk[np] = bk; Nf[np] = Bf[jb]; }
-        }
-        bsize = bsize + nc < ef ? bsize + nc : ef;
-        cur ^= 1;
-        wave_sync();
+        FG_TICK(3);
       }
     };
 
+    FG_TICK(6);
     process(A.roots, A.T);
     for (;;) {
       int first = -1;
@@ -324,6 +397,7 @@ __global__ void __launch_bounds__(64) k_beam(BeamArgs A) {
       uint32_t v = key_id(key);
       uint64_t s0 = A.off[v], s1 = A.off[v + 1];
       wave_sync();
+      FG_TICK(5);
       process(A.ids + s0, (int64_t)(s1 - s0));
     }
     my_evals += evals;
@@ -362,12 +436,15 @@ __global__ void __launch_bounds__(64) k_beam(BeamArgs A) {
         wave_sort_lds<uint64_t>(sk, M);
         int mc = 0;
         for (int base = 0; base < M; base += 64) mc += popc64(ballot(sk[base + lane] != FG_KEY_NONE));
+        FG_TICK(5);
         kept = prune_wave<DK, L, NCH>(X, A.alpha, A.R, sk, mc, S.alive, S.cid, S.ckey, out, &my_pe);
+        FG_TICK(4);
       }
       for (int t = kept + lane; t < A.R; t += 64) out[t] = FG_NONE;
       if (lane == 0) A.cnt[p] = (uint32_t)kept;
     }
 
+    FG_TICK(5);
     // Return the spill bitset to all-zero for the next query.
     if (spill) {
       my_spilled++;
@@ -383,8 +460,12 @@ __global__ void __launch_bounds__(64) k_beam(BeamArgs A) {
       __threadfence();
     }
     wave_sync();
+    FG_TICK(7);
   }
   if (lane == 0) {
+#ifdef FG_PROFILE
+    for (int i = 0; i < 8; i++) atomicAdd(&fg_prof_cycles[i], prof[i]);
+#endif
     atomicAdd(&A.counters[0], my_evals);
     atomicAdd(&A.counters[1], my_exp);
     atomicAdd(&A.counters[2], my_pe);

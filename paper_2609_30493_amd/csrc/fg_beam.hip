@@ -10,36 +10,37 @@ namespace fg {
 namespace {
 
 template <int DK, int L, int NCH, int EFMAX, bool SEARCH>
-void* kernel_ptr() {
-  return reinterpret_cast<void*>(&k_beam<DK, L, NCH, EFMAX, kHashSlots, SEARCH>);
+void* kernel_ptr(int hslots) {
+  if (hslots == 2048) return reinterpret_cast<void*>(&k_beam<DK, L, NCH, EFMAX, 2048, SEARCH>);
+  return reinterpret_cast<void*>(&k_beam<DK, L, NCH, EFMAX, 4096, SEARCH>);
 }
 
 template <int DK, int L, int NCH, bool SEARCH>
-void* pick_ef(int ef) {
+void* pick_ef(int ef, int hslots) {
   if constexpr (SEARCH) {
-    if (ef <= 128) return kernel_ptr<DK, L, NCH, 128, SEARCH>();
-    if (ef <= 512) return kernel_ptr<DK, L, NCH, 512, SEARCH>();
+    if (ef <= 128) return kernel_ptr<DK, L, NCH, 128, SEARCH>(4096);
+    if (ef <= 512) return kernel_ptr<DK, L, NCH, 512, SEARCH>(4096);
   } else {
-    if (ef <= 64) return kernel_ptr<DK, L, NCH, 64, SEARCH>();
-    if (ef <= 128) return kernel_ptr<DK, L, NCH, 128, SEARCH>();
-    if (ef <= 256) return kernel_ptr<DK, L, NCH, 256, SEARCH>();
+    if (ef <= 64) return kernel_ptr<DK, L, NCH, 64, SEARCH>(hslots);
+    if (ef <= 128) return kernel_ptr<DK, L, NCH, 128, SEARCH>(hslots);
+    if (ef <= 256) return kernel_ptr<DK, L, NCH, 256, SEARCH>(4096);
   }
   return nullptr;
 }
 
 template <bool SEARCH>
-void* pick(int dk, int Q, int ef) {
+void* pick(int dk, int Q, int ef, int hslots) {
   if (dk == U8L2) {
-    if (Q <= 8) return pick_ef<U8L2, 8, 1, SEARCH>(ef);
-    if (Q <= 16) return pick_ef<U8L2, 16, 1, SEARCH>(ef);
+    if (Q <= 8) return pick_ef<U8L2, 8, 1, SEARCH>(ef, hslots);
+    if (Q <= 16) return pick_ef<U8L2, 16, 1, SEARCH>(ef, hslots);
     return nullptr;
   }
-#define FG_F32_ROWS(DKV)                                         \
-  if (Q <= 8) return pick_ef<DKV, 8, 1, SEARCH>(ef);             \
-  if (Q <= 16) return pick_ef<DKV, 16, 1, SEARCH>(ef);           \
-  if (Q <= 32) return pick_ef<DKV, 16, 2, SEARCH>(ef);           \
-  if (Q <= 64) return pick_ef<DKV, 16, 4, SEARCH>(ef);           \
-  if (Q <= 256) return pick_ef<DKV, 16, 16, SEARCH>(ef);         \
+#define FG_F32_ROWS(DKV)                                                 \
+  if (Q <= 8) return pick_ef<DKV, 8, 1, SEARCH>(ef, hslots);             \
+  if (Q <= 16) return pick_ef<DKV, 16, 1, SEARCH>(ef, hslots);           \
+  if (Q <= 32) return pick_ef<DKV, 16, 2, SEARCH>(ef, hslots);           \
+  if (Q <= 64) return pick_ef<DKV, 16, 4, SEARCH>(ef, hslots);           \
+  if (Q <= 256) return pick_ef<DKV, 16, 16, SEARCH>(ef, hslots);         \
   return nullptr;
   if (dk == F32L2) { FG_F32_ROWS(F32L2) }
   if (dk == F32COS) { FG_F32_ROWS(F32COS) }
@@ -60,8 +61,16 @@ int num_cus() {
 
 }  // namespace
 
-int beam_grid(const Shape& s, int ef, bool search) {
-  void* k = search ? pick<true>(s.dk, s.Q, ef) : pick<false>(s.dk, s.Q, ef);
+// Slots of the on-chip visited table actually used for this launch: the
+// search kernels and ef > 128 always use 4096; otherwise `hslots` (2048 or
+// 4096) as requested.
+int beam_table_slots(int ef, bool search, int hslots) {
+  if (search || ef > 128) return 4096;
+  return hslots == 2048 ? 2048 : 4096;
+}
+
+int beam_grid(const Shape& s, int ef, bool search, int hslots) {
+  void* k = search ? pick<true>(s.dk, s.Q, ef, hslots) : pick<false>(s.dk, s.Q, ef, hslots);
   if (!k) return 0;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k), 64, 0) !=
@@ -72,11 +81,24 @@ int beam_grid(const Shape& s, int ef, bool search) {
   return g < kMaxWaveSlots ? g : kMaxWaveSlots;
 }
 
-hipError_t launch_beam(const Shape& s, BeamArgs& a, bool search, int grid, hipStream_t st) {
-  void* k = search ? pick<true>(s.dk, s.Q, a.ef) : pick<false>(s.dk, s.Q, a.ef);
+hipError_t launch_beam(const Shape& s, BeamArgs& a, bool search, int grid, int hslots, hipStream_t st) {
+  void* k = search ? pick<true>(s.dk, s.Q, a.ef, hslots) : pick<false>(s.dk, s.Q, a.ef, hslots);
   if (!k) return hipErrorInvalidValue;
   void* args[] = {&a};
   return hipLaunchKernel(reinterpret_cast<const void*>(k), dim3(grid), dim3(64), args, 0, st);
 }
 
+#ifdef FG_PROFILE
+__device__ unsigned long long fg_prof_cycles[16];
+#endif
+
 }  // namespace fg
+
+#ifdef FG_PROFILE
+// Profiling builds only: read and clear the phase cycle counters.
+extern "C" int fg_prof_read(unsigned long long* out16) {
+  if (hipMemcpyFromSymbol(out16, HIP_SYMBOL(fg::fg_prof_cycles), 16 * 8) != hipSuccess) return -1;
+  unsigned long long z[16] = {};
+  return hipMemcpyToSymbol(HIP_SYMBOL(fg::fg_prof_cycles), z, 16 * 8) == hipSuccess ? 0 : -1;
+}
+#endif

@@ -12,8 +12,8 @@
 namespace fg {
 
 // Bounds of the beam kernels' on-chip structures.
-constexpr int kHashSlots = 4096;         // LDS visited table per wave
-constexpr int kEcap = kHashSlots / 2;    // expanded entries per search
+constexpr int kHashSlotsMax = 4096;      // LDS visited table per wave (largest variant)
+constexpr int kEcap = kHashSlotsMax / 2; // expanded entries per search (buffer size)
 constexpr int kSpillCap = 8192;          // ids remembered for clearing the spill bitset
 constexpr int kMaxWaveSlots = 2048;      // persistent grid bound (wave slots)
 constexpr int kMaxEfHarvest = 256;
@@ -29,9 +29,12 @@ struct Shape {
 };
 bool make_shape(const fg_data* d, Shape* s);  // validates, sets error
 
-// Beam kernels (fg_beam.hip).  grid_for_beam() gives the persistent grid.
-int beam_grid(const Shape& s, int ef, bool search);
-hipError_t launch_beam(const Shape& s, BeamArgs& a, bool search, int grid, hipStream_t st);
+// Beam kernels (fg_beam.hip).  beam_grid() gives the persistent grid;
+// hslots is the requested on-chip visited-table size (2048 or 4096),
+// beam_table_slots() the size the chosen kernel really uses.
+int beam_table_slots(int ef, bool search, int hslots);
+int beam_grid(const Shape& s, int ef, bool search, int hslots);
+hipError_t launch_beam(const Shape& s, BeamArgs& a, bool search, int grid, int hslots, hipStream_t st);
 
 // Small utilities (fg_graph.hip).
 hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t st);

@@ -35,7 +35,7 @@ class fg_data(C.Structure):
 class fg_params(C.Structure):
     _fields_ = [("T", C.c_uint32), ("ef_h", C.c_uint32), ("R", C.c_uint32),
                 ("alpha", C.c_float), ("B", C.c_uint32), ("reprune_all", C.c_uint32),
-                ("reserved0", C.c_uint32), ("reserved1", C.c_uint32)]
+                ("beam_table_slots", C.c_uint32), ("reserved1", C.c_uint32)]
 
 
 class fg_csr(C.Structure):
@@ -145,8 +145,8 @@ def make_data(x: torch.Tensor, metric: str = "l2") -> fg_data:
     return s
 
 
-def make_params(T, ef_h, R, alpha=1.2, B=1, reprune_all=0) -> fg_params:
-    return fg_params(T, ef_h, R, alpha, B, reprune_all, 0, 0)
+def make_params(T, ef_h, R, alpha=1.2, B=1, reprune_all=0, beam_table_slots=0) -> fg_params:
+    return fg_params(T, ef_h, R, alpha, B, reprune_all, beam_table_slots, 0)
 
 
 def workspace_size(data: fg_data, params: fg_params) -> int:
