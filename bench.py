@@ -100,8 +100,62 @@ def cpu_baseline(w, n_sample: int, threads: int):
                       f"{wall:.1f} s wall, build {c['t_scaffold'] + c['t_harvest'] + c['t_merge'] + c['t_finalize']:.2f} s"}
 
 
+def dsweep(args):
+    """Tab. 4 re-measured: adaptive cost per evaluation (the harvest of a
+    whole build, T=8 B=8 ef_h=128 R=64) against blocked cost per pair (every
+    point's 64 nearest inside leaves of 2048 consecutive points on matrix
+    cores, float32 and bfloat16 operands), n = 200,000 power-law rows
+    truncated to each d."""
+    n = args.n or 200_000
+    out = []
+    for i, d in enumerate((32, 64, 128, 256, 512, 960)):
+        x = gen.powerlaw_f32(n, d, 500, 40 + i, d_total=960)
+        xd = torch.from_numpy(x).cuda()
+        data = F.make_data(xd)
+        params = F.make_params(8, 128, 64, 1.2, 8)
+        ws = F.alloc_workspace(data, params)
+        u32 = lambda *sh: torch.full(sh, -1, dtype=torch.int32, device="cuda")  # noqa: E731
+        G = F.make_graph(u32(n, 64), u32(n), u32(n), u32(8), 8)
+        F.build_graph(data, 42, params, G, ws, timings=True)
+        c, t = F.build_graph(data, 42, params, G, ws, timings=True)
+        del ws
+        rec = {"d": d, "n": n, "harvest_evals": c["harvest_evals"], "harvest_ms": t["harvest_ms"],
+               "adaptive_ns_per_eval": t["harvest_ms"] * 1e6 / c["harvest_evals"],
+               "build_ms": sum(t[k] for k in ("scaffold_ms", "harvest_ms", "merge_ms", "finalize_ms"))}
+        S, R = 2048, 64
+        pairs = sum(min(S, n - l0) ** 2 for l0 in range(0, n, S))
+        oi = torch.empty(n, R, dtype=torch.int32, device="cuda")
+        od = torch.empty(n, R, dtype=torch.float32, device="cuda")
+        for bf16 in (False, True):
+            lws = F.leaf_knn(data, S, R, bf16, oi, od)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            reps = 3
+            for _ in range(reps):
+                F.leaf_knn(data, S, R, bf16, oi, od, lws)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            key = "bf16" if bf16 else "fp32"
+            rec[f"blocked_{key}_ms"] = ms
+            rec[f"blocked_{key}_ns_per_pair"] = ms * 1e6 / pairs
+            rec[f"blocked_{key}_tflops"] = pairs * 2 * d / (ms / 1e3) / 1e12
+        rec["W_fp32"] = rec["adaptive_ns_per_eval"] / rec["blocked_fp32_ns_per_pair"]
+        log(f"[dsweep] {json.dumps(rec)}")
+        out.append(rec)
+        del xd, data, G
+        torch.cuda.empty_cache()
+    ds = np.log([r["d"] for r in out])
+    fit = {k: float(np.polyfit(ds, np.log([r[k] for r in out]), 1)[0])
+           for k in ("adaptive_ns_per_eval", "blocked_fp32_ns_per_pair", "blocked_bf16_ns_per_pair", "W_fp32")}
+    print(json.dumps({"mode": "dsweep", "n": n, "rows": out, "loglog_exponents": fit}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--mode", default="build", choices=("build", "dsweep"),
+                    help="build: the benchmark line (default); dsweep: wall vs dimension")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
@@ -119,6 +173,8 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(see DESIGN.md for how the harvest would shard).", file=sys.stderr)
         sys.exit(2)
+    if args.mode == "dsweep":
+        return dsweep(args)
 
     w = gen.CFG2
     n = args.n or w.n

@@ -208,6 +208,21 @@ fg_status fg_search(const fg_data* data, const fg_graph* graph,
  * Copies the graph to the host; synchronises `stream`. */
 fg_status fg_graph_hash(const fg_graph* graph, void* stream, uint64_t* out);
 
+/* The blocked dense side of the random-access wall (Sec. 5.3, Tab. 4): for
+ * every point, its R nearest other points (squared L2, ties by id) inside
+ * its leaf of leaf_size consecutive ids ([l*leaf_size, (l+1)*leaf_size)),
+ * all leaf_size^2 distances computed as |x|^2 + |y|^2 - 2<x,y> with the inner
+ * products on matrix cores: float32 operands (use_bf16 = 0) or operands
+ * rounded to bfloat16 (use_bf16 = 1, norms of the rounded rows), float32
+ * accumulation.  FG_F32 + FG_L2SQ data only; leaf_size a multiple of 128;
+ * 1 <= R <= 64.  Writes out_ids_dev / out_dists_dev (n x R, rows sorted,
+ * 0xFFFFFFFF / +inf padded when a leaf has fewer than R + 1 points).
+ * Asynchronous on `stream`. */
+size_t fg_leaf_knn_workspace_size(const fg_data* data);
+fg_status fg_leaf_knn(const fg_data* data, uint32_t leaf_size, uint32_t R,
+                      int use_bf16, uint32_t* out_ids_dev, float* out_dists_dev,
+                      void* ws_dev, size_t ws_bytes, void* stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* fg_last_error(void);
 

@@ -353,6 +353,28 @@ extern "C" {
 
 const char* fg_last_error(void) { return g_err.c_str(); }
 
+size_t fg_leaf_knn_workspace_size(const fg_data* data) {
+  if (!data || data->n < 1 || data->d < 1) return 0;
+  return leaf_knn_ws_bytes(data->n, data->d);
+}
+
+fg_status fg_leaf_knn(const fg_data* data, uint32_t leaf_size, uint32_t R, int use_bf16, uint32_t* out_ids_dev,
+                      float* out_dists_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+  Shape s;
+  if (!make_shape(data, &s)) return FG_EINVAL;
+  if (data->dtype != FG_F32 || data->metric != FG_L2SQ)
+    return set_error("fg_leaf_knn takes float32 squared-L2 data"), FG_EUNSUPPORTED;
+  if (leaf_size < 128 || leaf_size % 128 || leaf_size > 65536)
+    return set_error("leaf_size must be a multiple of 128 in [128, 65536]"), FG_EINVAL;
+  if (R < 1 || R > 64) return set_error("need 1 <= R <= 64"), FG_EINVAL;
+  if (!out_ids_dev || !out_dists_dev) return set_error("outputs are required"), FG_EINVAL;
+  if (!ws_dev || ws_bytes < leaf_knn_ws_bytes(s.n, s.d) || reinterpret_cast<uintptr_t>(ws_dev) % 256)
+    return set_error("workspace too small or misaligned (see fg_leaf_knn_workspace_size)"), FG_ENOMEM;
+  FG_HIP(leaf_knn(s, (int)leaf_size, (int)R, use_bf16 != 0, ws_dev, out_ids_dev, out_dists_dev,
+                  static_cast<hipStream_t>(stream)));
+  return FG_OK;
+}
+
 size_t fg_workspace_size(const fg_data* data, const fg_params* params) {
   if (!data || data->n < 1) return 0;
   return ws_map(data->n, params).total;

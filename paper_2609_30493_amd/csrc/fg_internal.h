@@ -103,4 +103,9 @@ struct FinalizeBig {
 };
 hipError_t launch_finalize(int dk, int Q, const FinalizeArgs& a, const FinalizeBig& big, hipStream_t st);
 
+// Leaf k-NN on MFMA (fg_dense.hip).
+size_t leaf_knn_ws_bytes(int64_t n, int d);
+hipError_t leaf_knn(const Shape& s, int S, int R, bool bf16, void* ws, uint32_t* out_ids, float* out_d,
+                    hipStream_t st);
+
 }  // namespace fg

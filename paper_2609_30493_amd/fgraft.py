@@ -86,6 +86,8 @@ _SIGS = {
     "fg_search": (C.c_int, [P, P, P, C.c_int64, C.c_uint32, C.c_uint32, P, P, P, P,
                             C.c_size_t, P]),
     "fg_graph_hash": (C.c_int, [P, P, P]),
+    "fg_leaf_knn_workspace_size": (C.c_size_t, [P]),
+    "fg_leaf_knn": (C.c_int, [P, C.c_uint32, C.c_uint32, C.c_int, P, P, P, C.c_size_t, P]),
 }
 
 
@@ -252,3 +254,15 @@ def graph_hash(graph: fg_graph, stream=None) -> int:
     h = C.c_uint64(0)
     _check(lib().fg_graph_hash(C.byref(graph), _stream(stream), C.byref(h)))
     return int(h.value)
+
+
+def leaf_knn(data: fg_data, leaf_size: int, R: int, use_bf16: bool, out_ids, out_d,
+             ws=None, stream=None):
+    """Every point's R nearest within its leaf of consecutive ids, on MFMA."""
+    if ws is None:
+        nb = int(lib().fg_leaf_knn_workspace_size(C.byref(data)))
+        ws = torch.empty(nb + 256, dtype=torch.uint8, device=out_ids.device)
+    wp, wn = _ws(ws)
+    _check(lib().fg_leaf_knn(C.byref(data), leaf_size, R, 1 if use_bf16 else 0, _ptr(out_ids),
+                             _ptr(out_d), wp, wn, _stream(stream)))
+    return ws
