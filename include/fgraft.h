@@ -57,6 +57,19 @@ typedef enum {
 typedef enum { FG_F32 = 0, FG_U8 = 1 } fg_dtype;
 typedef enum { FG_L2SQ = 0, FG_COSINE = 1 } fg_metric;
 
+/* Screened harvest (Sec. 5.3: an adaptive evaluation costs the bytes of one
+ * row).  FG_F32 data with d > 64 only.  A narrow copy of the rows (made in
+ * the workspace by the harvest entry points) gives every new candidate a
+ * cheap distance and a proven error margin; a candidate that provably cannot
+ * enter the full beam is not evaluated exactly.  Every other decision uses
+ * the exact float32 distance, so graphs, counts and hashes are those of
+ * FG_SCREEN_NONE. */
+typedef enum {
+  FG_SCREEN_NONE = 0,
+  FG_SCREEN_BF16 = 1,     /* bfloat16 copy, round to nearest even, 2d bytes/row */
+  FG_SCREEN_FP8E4M3 = 2   /* fp8 e4m3 (OCP) copy with a power-of-two scale per row, d bytes/row */
+} fg_screen;
+
 /* Row-major data in device memory.  FG_F32 needs d % 4 == 0; FG_U8 needs
  * d % 16 == 0 and FG_L2SQ.  row_stride_bytes is a multiple of 16 and at
  * least d * element size. */
@@ -76,7 +89,8 @@ typedef struct {
  * beam_table_slots is a tuning knob that never changes the graph: the size
  * of each harvest search's on-chip visited table, 2048 or 4096 (0 = 2048
  * when ef_h <= 128, else 4096; ef_h > 128 always uses 4096).  A search
- * whose expanded set exceeds half the table size fails with FG_ECAPACITY. */
+ * whose expanded set exceeds half the table size fails with FG_ECAPACITY.
+ * screen is an fg_screen; it never changes the graph either. */
 typedef struct {
   uint32_t T;
   uint32_t ef_h;
@@ -85,7 +99,7 @@ typedef struct {
   uint32_t B;
   uint32_t reprune_all;
   uint32_t beam_table_slots;
-  uint32_t reserved1;
+  uint32_t screen;
 } fg_params;
 
 /* Compressed rows in device memory: row v is ids_dev[off_dev[v] ..
@@ -124,6 +138,7 @@ typedef struct {
   uint64_t expansions;
   uint64_t finalize_evals;
   uint64_t spilled_queries; /* searches whose visited set left on-chip memory */
+  uint64_t screen_rejected; /* harvest evaluations settled by the screen alone (included in harvest_evals) */
 } fg_counters;
 
 /* Per-phase device time (HIP events on `stream`), milliseconds. */
@@ -132,13 +147,15 @@ typedef struct {
   float harvest_ms;      /* sum over blocks */
   float merge_ms;        /* sum over blocks */
   float finalize_ms;
+  float screen_ms;       /* making the narrow copy (screened builds) */
   float block_harvest_ms[64];
   uint64_t block_evals[64];
   uint32_t nblocks;
 } fg_timings;
 
 /* Bytes of device scratch needed by every entry point below for this data
- * shape and these parameters (one workspace serves all of them). */
+ * shape and these parameters (one workspace serves all of them; a screened
+ * harvest adds the narrow copy and three floats per row). */
 size_t fg_workspace_size(const fg_data* data, const fg_params* params);
 
 /* Keyed roots (Prop. 1, "keyed randomness"): root of tree t is the first
@@ -161,7 +178,8 @@ fg_status fg_build_scaffold(const fg_data* data, const uint32_t* roots_dev,
  * beam search of width ef_h over Sb from the T roots (roots_dev), then the
  * occlusion prune of the expanded set minus p into rows_dev[p*R ..] (n x R)
  * and row_cnt_dev[p].  Other rows are not touched.  counters (optional)
- * makes the call synchronise `stream`. */
+ * makes the call synchronise `stream`.  With params->screen set, the call
+ * first (re)makes the narrow copy of the data in the workspace. */
 fg_status fg_harvest_block(const fg_data* data, const fg_csr* Sb,
                            const uint32_t* roots_dev, const fg_params* params,
                            uint32_t b, uint32_t* rows_dev,
@@ -222,6 +240,20 @@ size_t fg_leaf_knn_workspace_size(const fg_data* data);
 fg_status fg_leaf_knn(const fg_data* data, uint32_t leaf_size, uint32_t R,
                       int use_bf16, uint32_t* out_ids_dev, float* out_dists_dev,
                       void* ws_dev, size_t ws_bytes, void* stream);
+
+/* The narrow copy a screened harvest reads (fg_screen), for inspection:
+ * row i of the data as bfloat16 (round to nearest even) or as fp8 e4m3 (OCP)
+ * codes of x * 2^k, k the largest integer with max|x_i| * 2^k <= 448, in
+ * the data's element order, rows fg_screen_row_bytes(d, screen) bytes apart
+ * (2d or d rounded up to a multiple of 16; pad bytes are not written).
+ * err_dev[i] >= |x^_i - x_i| and norm_dev[i] >= |x_i| (float64 sums rounded
+ * up), sinv_dev[i] = 2^-k (1 for bfloat16), where x^_i is the copy read
+ * back (fp8: code * 2^-k).  FG_F32 data with d > 64 only.  Asynchronous on
+ * `stream`. */
+int64_t fg_screen_row_bytes(int32_t d, uint32_t screen);
+fg_status fg_screen_copy(const fg_data* data, uint32_t screen, void* xs_dev,
+                         float* err_dev, float* norm_dev, float* sinv_dev,
+                         void* stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* fg_last_error(void);

@@ -59,6 +59,15 @@ bool check_params(const fg_params* p, int64_t n, bool need_ef = true) {
   if (!isfinite(p->alpha) || p->alpha < 1.0f) return set_error("alpha must be finite and >= 1"), false;
   if (p->beam_table_slots != 0 && p->beam_table_slots != 2048 && p->beam_table_slots != 4096)
     return set_error("beam_table_slots must be 0, 2048 or 4096"), false;
+  if (p->screen > FG_SCREEN_FP8E4M3) return set_error("screen must be an fg_screen"), false;
+  return true;
+}
+
+// The screened kernels exist for float32 rows of 17..256 chunks.
+bool check_screen(const fg_params* p, const Shape& s) {
+  if (p->screen == FG_SCREEN_NONE) return true;
+  if (s.dk == U8L2) return set_error("screening applies to FG_F32 data only"), false;
+  if (s.Q <= 16 || s.Q > 256) return set_error("screening needs 64 < d <= 1024"), false;
   return true;
 }
 
@@ -82,6 +91,8 @@ struct WsMap {
   size_t sgoff, sgids;                      // search graph
   size_t off[2], ids[2], rows, cnt, tparent, roots;  // the whole build
   size_t sat;
+  size_t xs, xs_err, xs_norm, xs_sinv;      // screened harvest (last: only they depend on d)
+  int64_t xs_stride;
   SatWs satw;
   size_t total;
   int64_t spill_words;
@@ -90,7 +101,7 @@ struct WsMap {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-WsMap ws_map(int64_t n, const fg_params* p) {
+WsMap ws_map(int64_t n, const fg_params* p, int d = 0) {
   WsMap m{};
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -136,6 +147,13 @@ WsMap ws_map(int64_t n, const fg_params* p) {
   m.roots = take(64 * 4);
   sat_workspace_bytes(n, (uint32_t)T, &m.satw);
   m.sat = take(m.satw.total);
+  if (p && p->screen && d > 0) {
+    m.xs_stride = screen_stride(d, (int)p->screen);
+    m.xs = take(un * (uint64_t)m.xs_stride);
+    m.xs_err = take(un * 4);
+    m.xs_norm = take(un * 4);
+    m.xs_sinv = take(un * 4);
+  }
   m.total = o;
   return m;
 }
@@ -143,7 +161,7 @@ WsMap ws_map(int64_t n, const fg_params* p) {
 // ctl region: [0] queue, [1..4] beam counters, [8] status (int)
 struct Ctl {
   unsigned long long queue;
-  unsigned long long counters[4];    // beam: evals, expansions, prune pairs, spilled
+  unsigned long long counters[5];    // beam: evals, expansions, prune pairs, spilled, screen-rejected
   unsigned long long fin[2];         // finalize: candidate distances, prune pairs
   uint32_t nbig, pad32;              // rows sent to the big-row paths
   int status;                        // 1 expanded-set overflow
@@ -180,7 +198,8 @@ fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* id
   FG_HIP(fill_u64(reinterpret_cast<uint64_t*>(&ctl->queue), 0, 1, st));
   if (nitems == 0) return FG_OK;
   const int hslots = beam_table_slots((int)P->ef_h, false, table_request(P));
-  int grid = beam_grid(s, (int)P->ef_h, false, hslots);
+  const int screen = (int)P->screen;
+  int grid = beam_grid(s, (int)P->ef_h, false, hslots, screen);
   if (grid <= 0) return set_error("no beam kernel for this row size / ef_h"), FG_EUNSUPPORTED;
   BeamArgs a{};
   a.x = s.x;
@@ -208,7 +227,23 @@ fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* id
   a.spill_cap = kSpillCap;
   a.counters = ctl->counters;
   a.status = &ctl->status;
-  FG_HIP(launch_beam(s, a, false, grid, hslots, st));
+  a.d = s.d;
+  if (screen) {
+    a.xs = reinterpret_cast<const uint8_t*>(at(ws, m.xs));
+    a.xs_stride = m.xs_stride;
+    a.xs_err = reinterpret_cast<const float*>(at(ws, m.xs_err));
+    a.xs_norm = reinterpret_cast<const float*>(at(ws, m.xs_norm));
+    a.xs_sinv = reinterpret_cast<const float*>(at(ws, m.xs_sinv));
+  }
+  FG_HIP(launch_beam(s, a, false, grid, hslots, st, screen));
+  return FG_OK;
+}
+
+fg_status screen_launch(const Shape& s, const fg_params* P, void* ws, const WsMap& m, hipStream_t st) {
+  if (!P->screen) return FG_OK;
+  FG_HIP(make_screen(s, (int)P->screen, reinterpret_cast<uint8_t*>(at(ws, m.xs)),
+                     reinterpret_cast<float*>(at(ws, m.xs_err)), reinterpret_cast<float*>(at(ws, m.xs_norm)),
+                     reinterpret_cast<float*>(at(ws, m.xs_sinv)), st));
   return FG_OK;
 }
 
@@ -375,9 +410,30 @@ fg_status fg_leaf_knn(const fg_data* data, uint32_t leaf_size, uint32_t R, int u
   return FG_OK;
 }
 
+int64_t fg_screen_row_bytes(int32_t d, uint32_t screen) {
+  if (d < 1 || (screen != FG_SCREEN_BF16 && screen != FG_SCREEN_FP8E4M3)) return 0;
+  return screen_stride(d, (int)screen);
+}
+
+fg_status fg_screen_copy(const fg_data* data, uint32_t screen, void* xs_dev, float* err_dev, float* norm_dev,
+                         float* sinv_dev, void* stream) {
+  Shape s;
+  if (!make_shape(data, &s)) return FG_EINVAL;
+  if (screen != FG_SCREEN_BF16 && screen != FG_SCREEN_FP8E4M3)
+    return set_error("screen must be FG_SCREEN_BF16 or FG_SCREEN_FP8E4M3"), FG_EINVAL;
+  fg_params P{};
+  P.screen = screen;
+  if (!check_screen(&P, s)) return FG_EUNSUPPORTED;
+  if (!xs_dev || !err_dev || !norm_dev || !sinv_dev) return set_error("NULL output"), FG_EINVAL;
+  if (reinterpret_cast<uintptr_t>(xs_dev) % 16) return set_error("xs_dev must be 16-byte aligned"), FG_EINVAL;
+  FG_HIP(make_screen(s, (int)screen, static_cast<uint8_t*>(xs_dev), err_dev, norm_dev, sinv_dev,
+                     static_cast<hipStream_t>(stream)));
+  return FG_OK;
+}
+
 size_t fg_workspace_size(const fg_data* data, const fg_params* params) {
   if (!data || data->n < 1) return 0;
-  return ws_map(data->n, params).total;
+  return ws_map(data->n, params, data->d).total;
 }
 
 fg_status fg_roots(uint64_t seed, int64_t n, uint32_t T, uint32_t* roots) {
@@ -410,10 +466,13 @@ fg_status fg_harvest_block(const fg_data* data, const fg_csr* Sb, const uint32_t
     return set_error("Sb must be a CSR over the data's n points"), FG_EINVAL;
   if (!roots_dev || !rows_dev || !row_cnt_dev) return set_error("NULL output or roots"), FG_EINVAL;
   if (b >= b_eff(params)) return set_error("need b < max(B, 1)"), FG_EINVAL;
-  WsMap m = ws_map(s.n, params);
+  if (!check_screen(params, s)) return FG_EUNSUPPORTED;
+  WsMap m = ws_map(s.n, params, s.d);
   if (!check_ws(ws_dev, ws_bytes, m)) return FG_ENOMEM;
   hipStream_t st = static_cast<hipStream_t>(stream);
   fg_status r = reset_ctl(ws_dev, m, st);
+  if (r) return r;
+  r = screen_launch(s, params, ws_dev, m, st);
   if (r) return r;
   FG_HIP(fill_u32(reinterpret_cast<uint32_t*>(at(ws_dev, m.bits)), 0,
                   (int64_t)kMaxWaveSlots * m.spill_words, st));
@@ -428,6 +487,7 @@ fg_status fg_harvest_block(const fg_data* data, const fg_csr* Sb, const uint32_t
     counters->expansions += c.counters[1];
     counters->prune_evals += c.counters[2];
     counters->spilled_queries += c.counters[3];
+    counters->screen_rejected += c.counters[4];
     return status_error(c.status);
   }
   return FG_OK;
@@ -645,7 +705,8 @@ fg_status fg_build_graph(const fg_data* data, uint64_t seed, const fg_params* pa
     return set_error("output graph shape does not match data/params"), FG_EINVAL;
   const uint32_t Be = b_eff(params);
   if (timings && Be > 64) return set_error("timings record at most 64 blocks"), FG_EINVAL;
-  WsMap m = ws_map(s.n, params);
+  if (!check_screen(params, s)) return FG_EUNSUPPORTED;
+  WsMap m = ws_map(s.n, params, s.d);
   if (!check_ws(ws_dev, ws_bytes, m)) return FG_ENOMEM;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t n = s.n;
@@ -691,6 +752,8 @@ fg_status fg_build_graph(const fg_data* data, uint64_t seed, const fg_params* pa
   FG_TRY(scaffold_csr_launch(n, T, tparent, off[0], ids[0], ws_dev, m, st));
   FG_HIP(hipMemcpyAsync(out->spine_parent_dev, tparent, n * 4, hipMemcpyDeviceToDevice, st));
   FG_TRY(mark());
+  FG_TRY(screen_launch(s, params, ws_dev, m, st));
+  FG_TRY(mark());
 
   // Blocks.
   FG_HIP(fill_u32(rows, FG_NONE, n * (int64_t)R, st));
@@ -728,6 +791,7 @@ fg_status fg_build_graph(const fg_data* data, uint64_t seed, const fg_params* pa
     counters->expansions += c.counters[1];
     counters->prune_evals += c.counters[2];
     counters->spilled_queries += c.counters[3];
+    counters->screen_rejected += c.counters[4];
     counters->finalize_evals += c.fin[0] + c.fin[1];
   }
   if (timings) {
@@ -738,10 +802,11 @@ fg_status fg_build_graph(const fg_data* data, uint64_t seed, const fg_params* pa
       return t;
     };
     timings->scaffold_ms = ms(0, 1);
+    timings->screen_ms = ms(1, 2);
     timings->nblocks = Be;
     unsigned long long prev = 0;
     for (uint32_t b = 0; b < Be; b++) {
-      int i0 = 2 + 3 * b;
+      int i0 = 3 + 3 * b;
       float h = ms(i0, i0 + 1);
       timings->block_harvest_ms[b] = h;
       timings->harvest_ms += h;
@@ -749,7 +814,7 @@ fg_status fg_build_graph(const fg_data* data, uint64_t seed, const fg_params* pa
       timings->block_evals[b] = blk_evals[b] - prev;
       prev = blk_evals[b];
     }
-    timings->finalize_ms = ms(1 + 3 * Be, 2 + 3 * Be);
+    timings->finalize_ms = ms(2 + 3 * Be, 3 + 3 * Be);
   }
   cleanup();
 #undef FG_TRY

@@ -17,6 +17,14 @@
 // it is 3/4 full, further ids go to a per-wave bitset in device memory (and a
 // list of them, so the bitset can be cleared word by word afterwards).
 //
+// Screened harvest (float32 rows, Sec. 5.3's bytes-per-evaluation term): a
+// narrow copy of the rows (bfloat16, or fp8-e4m3 with a power-of-two scale
+// per row) gives each new candidate a cheap distance d~ and a rigorous error
+// margin eps; once the beam is full, a candidate with d~ - eps above the
+// beam's worst exact distance cannot enter it and is not evaluated exactly.
+// Every other candidate gets its exact float32 distance, so the beam, the
+// expanded set and the graph are those of the unscreened search.
+//
 // Harvest mode records the expanded entries and then prunes them (without
 // the query point itself): sorted by key, the next live candidate is kept,
 // and every later live candidate c with fl32(alpha * d(kept, c)) <= d(p, c)
@@ -82,9 +90,135 @@ struct BeamArgs {
   int64_t spill_words;
   uint32_t* spill_list;
   int spill_cap;
-  unsigned long long* counters;  // evals, expansions, prune pairs, spilled
+  unsigned long long* counters;  // evals, expansions, prune pairs, spilled, screen-rejected
   int* status;                   // bit 0: expanded-list overflow
+  // screened harvest: the narrow copy (row stride xs_stride bytes, the
+  // elements in data order), per row the norm of its quantisation error
+  // |u^ - u|, its norm |u| (both rounded up) and the fp8 dequantisation
+  // factor (a power of two)
+  const uint8_t* xs;
+  int64_t xs_stride;
+  const float* xs_err;
+  const float* xs_norm;
+  const float* xs_sinv;
+  int d;
 };
+
+enum ScreenKind { SCR_NONE = 0, SCR_BF16 = 1, SCR_FP8 = 2 };
+
+// Screened distance between the query's exact float32 chunks `a` and row
+// `srow` of the narrow copy (lane g reads the narrow form of its own chunks
+// q = g + L*i), reduced over the group.  Any summation order: the margin
+// below holds for all of them.
+template <int DK, int L, int NCH, int SCR>
+__device__ __forceinline__ float group_screen(const Chunks<L, NCH>& a, const uint8_t* srow, float sinv, int Q,
+                                              int g) {
+  float acc = 0.0f;
+#pragma unroll
+  for (int i = 0; i < NCH; i++) {
+    const int q = g + L * i;
+    if (q < Q) {
+      const float4 xa = *reinterpret_cast<const float4*>(&a.c[i]);
+      float4 xb;
+      if constexpr (SCR == SCR_BF16) {
+        const uint2 w = *reinterpret_cast<const uint2*>(srow + 8 * (size_t)q);
+        xb = make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xFFFF0000u), __uint_as_float(w.y << 16),
+                         __uint_as_float(w.y & 0xFFFF0000u));
+      } else {
+        const int w = *reinterpret_cast<const int*>(srow + 4 * (size_t)q);
+        const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8(w, false);
+        const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8(w, true);
+        xb = make_float4(lo[0] * sinv, lo[1] * sinv, hi[0] * sinv, hi[1] * sinv);
+      }
+      if constexpr (DK == F32L2) {
+        const float d0 = xa.x - xb.x, d1 = xa.y - xb.y, d2 = xa.z - xb.z, d3 = xa.w - xb.w;
+        acc = __builtin_fmaf(d0, d0, acc);
+        acc = __builtin_fmaf(d1, d1, acc);
+        acc = __builtin_fmaf(d2, d2, acc);
+        acc = __builtin_fmaf(d3, d3, acc);
+      } else {
+        acc = __builtin_fmaf(xa.x, xb.x, acc);
+        acc = __builtin_fmaf(xa.y, xb.y, acc);
+        acc = __builtin_fmaf(xa.z, xb.z, acc);
+        acc = __builtin_fmaf(xa.w, xb.w, acc);
+      }
+    }
+  }
+#pragma unroll
+  for (int off = L / 2; off >= 1; off >>= 1) acc = acc + __shfl_xor(acc, off, 64);
+  if constexpr (DK == F32COS) acc = 1.0f - acc;
+  return acc;
+}
+
+// Margin eps such that the exact (declared-order float32) distance is at
+// least dt - eps, for a screened value dt (standard rounding-error analysis,
+// unit roundoff u = 2^-24; gs bounds the screened sum's relative error over
+// d + 12 roundings, gc the declared order's over d/16 + 8):
+//   squared L2: with A = sqrt(dt / (1 - gs)) >= |p - u^|, |p - u| >= A' - E
+//     where E = |u^ - u|, so exact >= dt - (gs + gc) dt - 2 A E;
+//   cosine: |<p,u^> - <p,u>| <= |p| E, both sums' errors are within
+//     (gs + gc) |p| (|u| + E), and the two roundings of 1 - s add
+//     2^-23 (1 + |p| (|u| + E)).
+// The result is doubled, which also covers the rounding of eps itself.
+template <int DK>
+__device__ __forceinline__ float screen_eps(float dt, int d, float E, float np, float nu) {
+  const float u = 5.9604645e-08f;  // 2^-24
+  const float gs = (d + 12) * u / (1.0f - (d + 12) * u);
+  const float gc = (d / 16 + 8) * u / (1.0f - (d / 16 + 8) * u);
+  float eps;
+  if constexpr (DK == F32L2) {
+    const float dd = dt > 0.0f ? dt : 0.0f;
+    const float A = __builtin_sqrtf(dd / (1.0f - gs)) * (1.0f + 4.0f * u);
+    eps = (gs + gc) * dd + 2.0f * A * E;
+  } else {
+    const float pu = np * (nu + E);
+    eps = np * E + (gs + gc) * pu + 2.0f * u * 2.0f * (1.0f + pu);
+  }
+  return 2.0f * eps;
+}
+
+// Screen the cnt new ids in ids_lds (cnt <= 256) against the beam's worst
+// exact distance w: ids that cannot enter the beam are dropped, the others
+// are compacted (in order) to the front of ids_lds.  Returns their number.
+template <int DK, int L, int NCH, int SCR>
+__device__ __forceinline__ int screen_filter(const BeamArgs& A, const Chunks<L, NCH>& a, float np,
+                                             uint32_t* ids_lds, int cnt, float w) {
+  constexpr int G = 64 / L;
+  constexpr int RB = (NCH >= 16) ? 1 : 16 / NCH;
+  const int lane = lane_id();
+  const int grp = lane / L, g = lane % L;
+  int kept = 0;
+  for (int r0 = 0; r0 < cnt; r0 += G * RB) {
+    uint32_t u[RB];
+    float dt[RB];
+#pragma unroll
+    for (int t = 0; t < RB; t++) {
+      const int r = r0 + t * G + grp;
+      u[t] = ids_lds[r < cnt ? r : 0];
+    }
+#pragma unroll
+    for (int t = 0; t < RB; t++) {
+      const float sinv = SCR == SCR_FP8 ? A.xs_sinv[u[t]] : 1.0f;
+      dt[t] = group_screen<DK, L, NCH, SCR>(a, A.xs + (size_t)u[t] * A.xs_stride, sinv, A.Q, g);
+    }
+    wave_sync();
+#pragma unroll
+    for (int t = 0; t < RB; t++) {
+      const int r = r0 + t * G + grp;
+      bool keep = false;
+      if (r < cnt && g == 0) {
+        const float nu = DK == F32COS ? A.xs_norm[u[t]] : 0.0f;
+        const float eps = screen_eps<DK>(dt[t], A.d, A.xs_err[u[t]], np, nu);
+        keep = !(dt[t] - eps > w);
+      }
+      const uint64_t m = ballot(keep);
+      if (keep) ids_lds[kept + popc64(m & lanes_below())] = u[t];
+      kept += popc64(m);
+    }
+    wave_sync();
+  }
+  return kept;
+}
 
 template <int EFMAX, int HSLOTS>
 struct WaveLDS {
@@ -230,7 +364,7 @@ __device__ int prune_wave(const RowSet& X, float alpha, int R, const uint64_t* s
   return kept;
 }
 
-template <int DK, int L, int NCH, int EFMAX, int HSLOTS, bool SEARCH>
+template <int DK, int L, int NCH, int EFMAX, int HSLOTS, bool SEARCH, int SCR = SCR_NONE>
 __global__ void __launch_bounds__(64) k_beam(BeamArgs A) {
   __shared__ WaveLDS<EFMAX, HSLOTS> S;
   const int lane = lane_id();
@@ -245,7 +379,7 @@ __global__ void __launch_bounds__(64) k_beam(BeamArgs A) {
   const int ef = A.ef;
   const RowSet X{A.x, A.stride, A.Q};
 
-  unsigned long long my_evals = 0, my_exp = 0, my_pe = 0, my_spilled = 0;
+  unsigned long long my_evals = 0, my_exp = 0, my_pe = 0, my_spilled = 0, my_rej = 0;
 #ifdef FG_PROFILE
   unsigned long long prof[16] = {};
 #endif
@@ -263,6 +397,8 @@ __global__ void __launch_bounds__(64) k_beam(BeamArgs A) {
     load_chunks<L, NCH>(qc, qrow, A.Q, g);
     uint32_t qn = 0;
     if constexpr (DK == U8L2) qn = group_sum_u32<L>(u8_selfdot<L, NCH>(qc));
+    float qnorm = 0.0f;  // |p| for the cosine screen margin
+    if constexpr (SCR != SCR_NONE && DK == F32COS) qnorm = A.xs_norm[p];
 
     for (int i = lane; i < HSLOTS; i += 64) S.htab[i] = FG_NONE;
     if (lane == 0) S.nspill = 0;
@@ -343,6 +479,15 @@ __global__ void __launch_bounds__(64) k_beam(BeamArgs A) {
         evals += (unsigned long long)nnew;
         if (nnew == 0) continue;
         wave_sync();
+        if constexpr (SCR != SCR_NONE) {
+          if (bsize == ef) {  // a full beam: its worst exact distance bounds entry
+            const float w = ord_to_f32(key_hi(S.bkeys[cur][ef - 1]));
+            const int nx = screen_filter<DK, L, NCH, SCR>(A, qc, qnorm, S.sid, nnew, w);
+            my_rej += (unsigned long long)(nnew - nx);
+            nnew = nx;
+            if (nnew == 0) continue;
+          }
+        }
         batch_dists_rs<DK, L, NCH, kRB>(X, qc, qn, S.sid, nnew, S.skey);
         FG_TICK(2);
         for (int c0 = 0; c0 < nnew; c0 += 64) {
@@ -470,6 +615,7 @@ __global__ void __launch_bounds__(64) k_beam(BeamArgs A) {
     atomicAdd(&A.counters[1], my_exp);
     atomicAdd(&A.counters[2], my_pe);
     atomicAdd(&A.counters[3], my_spilled);
+    if (my_rej) atomicAdd(&A.counters[4], my_rej);
   }
 }
 

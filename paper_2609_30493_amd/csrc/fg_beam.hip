@@ -69,8 +69,14 @@ int beam_table_slots(int ef, bool search, int hslots) {
   return hslots == 2048 ? 2048 : 4096;
 }
 
-int beam_grid(const Shape& s, int ef, bool search, int hslots) {
-  void* k = search ? pick<true>(s.dk, s.Q, ef, hslots) : pick<false>(s.dk, s.Q, ef, hslots);
+static void* pick_kernel(const Shape& s, int ef, bool search, int hslots, int screen) {
+  if (screen == SCR_BF16) return search ? nullptr : pick_screen_bf16(s.dk, s.Q, ef, hslots);
+  if (screen == SCR_FP8) return search ? nullptr : pick_screen_fp8(s.dk, s.Q, ef, hslots);
+  return search ? pick<true>(s.dk, s.Q, ef, hslots) : pick<false>(s.dk, s.Q, ef, hslots);
+}
+
+int beam_grid(const Shape& s, int ef, bool search, int hslots, int screen) {
+  void* k = pick_kernel(s, ef, search, hslots, screen);
   if (!k) return 0;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k), 64, 0) !=
@@ -81,8 +87,9 @@ int beam_grid(const Shape& s, int ef, bool search, int hslots) {
   return g < kMaxWaveSlots ? g : kMaxWaveSlots;
 }
 
-hipError_t launch_beam(const Shape& s, BeamArgs& a, bool search, int grid, int hslots, hipStream_t st) {
-  void* k = search ? pick<true>(s.dk, s.Q, a.ef, hslots) : pick<false>(s.dk, s.Q, a.ef, hslots);
+hipError_t launch_beam(const Shape& s, BeamArgs& a, bool search, int grid, int hslots, hipStream_t st,
+                       int screen) {
+  void* k = pick_kernel(s, a.ef, search, hslots, screen);
   if (!k) return hipErrorInvalidValue;
   void* args[] = {&a};
   return hipLaunchKernel(reinterpret_cast<const void*>(k), dim3(grid), dim3(64), args, 0, st);

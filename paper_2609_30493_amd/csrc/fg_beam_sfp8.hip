@@ -1,0 +1,41 @@
+// fg_beam_sfp8.hip -- the screened harvest kernels with the fp8 narrow copy
+// (float32 rows of more than 16 chunks, L = 16 lanes per row).
+#include "fg_internal.h"
+
+namespace fg {
+
+namespace {
+
+template <int DK, int NCH, int EFMAX>
+void* kp(int hslots) {
+  if constexpr (EFMAX <= 128)
+    if (hslots == 2048) return reinterpret_cast<void*>(&k_beam<DK, 16, NCH, EFMAX, 2048, false, SCR_FP8>);
+  return reinterpret_cast<void*>(&k_beam<DK, 16, NCH, EFMAX, 4096, false, SCR_FP8>);
+}
+
+template <int DK, int NCH>
+void* pick_ef(int ef, int hslots) {
+  if (ef <= 64) return kp<DK, NCH, 64>(hslots);
+  if (ef <= 128) return kp<DK, NCH, 128>(hslots);
+  if (ef <= 256) return kp<DK, NCH, 256>(4096);
+  return nullptr;
+}
+
+template <int DK>
+void* pick_q(int Q, int ef, int hslots) {
+  if (Q <= 16) return nullptr;
+  if (Q <= 32) return pick_ef<DK, 2>(ef, hslots);
+  if (Q <= 64) return pick_ef<DK, 4>(ef, hslots);
+  if (Q <= 256) return pick_ef<DK, 16>(ef, hslots);
+  return nullptr;
+}
+
+}  // namespace
+
+void* pick_screen_fp8(int dk, int Q, int ef, int hslots) {
+  if (dk == F32L2) return pick_q<F32L2>(Q, ef, hslots);
+  if (dk == F32COS) return pick_q<F32COS>(Q, ef, hslots);
+  return nullptr;
+}
+
+}  // namespace fg

@@ -32,9 +32,20 @@ bool make_shape(const fg_data* d, Shape* s);  // validates, sets error
 // Beam kernels (fg_beam.hip).  beam_grid() gives the persistent grid;
 // hslots is the requested on-chip visited-table size (2048 or 4096),
 // beam_table_slots() the size the chosen kernel really uses.
+// screen (ScreenKind) selects the screened harvest kernels (fg_beam_sbf16.hip,
+// fg_beam_sfp8.hip: float32 rows of more than 16 chunks only).
 int beam_table_slots(int ef, bool search, int hslots);
-int beam_grid(const Shape& s, int ef, bool search, int hslots);
-hipError_t launch_beam(const Shape& s, BeamArgs& a, bool search, int grid, int hslots, hipStream_t st);
+int beam_grid(const Shape& s, int ef, bool search, int hslots, int screen = SCR_NONE);
+hipError_t launch_beam(const Shape& s, BeamArgs& a, bool search, int grid, int hslots, hipStream_t st,
+                       int screen = SCR_NONE);
+void* pick_screen_bf16(int dk, int Q, int ef, int hslots);
+void* pick_screen_fp8(int dk, int Q, int ef, int hslots);
+
+// Narrow copies for the screened harvest (fg_screen.hip): row stride in
+// bytes, and the copy with its per-row error norm, norm and fp8 factor.
+int64_t screen_stride(int d, int screen);
+hipError_t make_screen(const Shape& s, int screen, uint8_t* xs, float* err, float* norm, float* sinv,
+                       hipStream_t st);
 
 // Small utilities (fg_graph.hip).
 hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t st);

@@ -1,0 +1,140 @@
+// fg_screen.hip -- the narrow copy of float32 rows that the screened harvest
+// reads first (Sec. 5.3: the harvest's cost per evaluation is the bytes of
+// one row; a half- or quarter-width copy rejects most candidates at a
+// fraction of them).
+//
+// One wave per row.  bfloat16: round to nearest even.  fp8-e4m3 (OCP): the
+// row is scaled by the power of two 2^k that brings its largest magnitude
+// to at most 448, converted by the hardware, and read back as
+// code * 2^-k.  For every row the norm of the actual error |u^ - u| and the
+// norm |u| are accumulated in float64 and rounded up to float32, so the
+// margin the search uses bounds the copy that the search reads, whatever
+// rounding the conversion did.
+#include "fg_internal.h"
+
+namespace fg {
+
+namespace {
+
+// v >= 0: the float32 value next above or equal to v
+__device__ __forceinline__ float round_up_f32(double v) {
+  float f = (float)v;
+  if ((double)f < v) f = __uint_as_float(__float_as_uint(f) + 1u);
+  return f;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ float wave_max_f32(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+  const uint32_t b = __float_as_uint(f);
+  return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+
+// Elements are handled four at a time (d % 4 == 0): element 4c..4c+3 by
+// lane c mod 64.
+template <int SCR>
+__global__ void __launch_bounds__(256) k_make_screen(const uint8_t* x, int64_t stride, int64_t n, int d,
+                                                     uint8_t* xs, int64_t xs_stride, float* err, float* norm,
+                                                     float* sinv) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int C = d / 4;
+  for (int64_t i = wave; i < n; i += nwaves) {
+    const float* row = reinterpret_cast<const float*>(x + i * stride);
+    float scale = 1.0f, inv = 1.0f;
+    if constexpr (SCR == SCR_FP8) {
+      float mx = 0.0f;
+      for (int c = lane; c < C; c += 64) {
+        const float4 v = *reinterpret_cast<const float4*>(row + 4 * c);
+        mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+      }
+      mx = wave_max_f32(mx);
+      int k = 0;
+      if (mx > 0.0f) {
+        // largest k with mx * 2^k <= 448
+        k = (int)floor(log2(448.0 / (double)mx));
+        while (ldexp((double)mx, k) > 448.0) k--;
+        while (ldexp((double)mx, k + 1) <= 448.0) k++;
+        if (k > 100) k = 100;
+        if (k < -100) k = -100;
+      }
+      scale = ldexpf(1.0f, k);
+      inv = ldexpf(1.0f, -k);
+    }
+    double e2 = 0.0, n2 = 0.0;
+    for (int c = lane; c < C; c += 64) {
+      const float4 v = *reinterpret_cast<const float4*>(row + 4 * c);
+      const float a[4] = {v.x, v.y, v.z, v.w};
+      float back[4];
+      if constexpr (SCR == SCR_BF16) {
+        uint16_t h[4];
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          h[t] = bf16_rne(a[t]);
+          back[t] = __uint_as_float((uint32_t)h[t] << 16);
+        }
+        uint2 w;
+        w.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+        w.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+        *reinterpret_cast<uint2*>(xs + i * xs_stride + 8 * (int64_t)c) = w;
+      } else {
+        int w = __builtin_amdgcn_cvt_pk_fp8_f32(a[0] * scale, a[1] * scale, 0, false);
+        w = __builtin_amdgcn_cvt_pk_fp8_f32(a[2] * scale, a[3] * scale, w, true);
+        const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8(w, false);
+        const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8(w, true);
+        back[0] = lo[0] * inv;
+        back[1] = lo[1] * inv;
+        back[2] = hi[0] * inv;
+        back[3] = hi[1] * inv;
+        *reinterpret_cast<int*>(xs + i * xs_stride + 4 * (int64_t)c) = w;
+      }
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        const double e = (double)back[t] - (double)a[t];
+        e2 += e * e;
+        n2 += (double)a[t] * (double)a[t];
+      }
+    }
+    e2 = wave_sum_f64(e2);
+    n2 = wave_sum_f64(n2);
+    if (lane == 0) {
+      // the float64 sums carry a relative error far below 2^-30
+      err[i] = round_up_f32(sqrt(e2) * (1.0 + 0x1p-30));
+      norm[i] = round_up_f32(sqrt(n2) * (1.0 + 0x1p-30));
+      sinv[i] = inv;
+    }
+  }
+}
+
+}  // namespace
+
+int64_t screen_stride(int d, int screen) {
+  const int64_t b = screen == SCR_BF16 ? 2 * (int64_t)d : (int64_t)d;
+  return (b + 15) / 16 * 16;
+}
+
+hipError_t make_screen(const Shape& s, int screen, uint8_t* xs, float* err, float* norm, float* sinv,
+                       hipStream_t st) {
+  const int64_t xst = screen_stride(s.d, screen);
+  int64_t blocks = (s.n + 3) / 4;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  if (screen == SCR_BF16)
+    k_make_screen<SCR_BF16><<<(unsigned)blocks, 256, 0, st>>>(s.x, s.stride, s.n, s.d, xs, xst, err, norm, sinv);
+  else
+    k_make_screen<SCR_FP8><<<(unsigned)blocks, 256, 0, st>>>(s.x, s.stride, s.n, s.d, xs, xst, err, norm, sinv);
+  return hipGetLastError();
+}
+
+}  // namespace fg

@@ -35,7 +35,10 @@ class fg_data(C.Structure):
 class fg_params(C.Structure):
     _fields_ = [("T", C.c_uint32), ("ef_h", C.c_uint32), ("R", C.c_uint32),
                 ("alpha", C.c_float), ("B", C.c_uint32), ("reprune_all", C.c_uint32),
-                ("beam_table_slots", C.c_uint32), ("reserved1", C.c_uint32)]
+                ("beam_table_slots", C.c_uint32), ("screen", C.c_uint32)]
+
+
+SCREEN_NONE, SCREEN_BF16, SCREEN_FP8E4M3 = 0, 1, 2
 
 
 class fg_csr(C.Structure):
@@ -52,7 +55,8 @@ class fg_graph(C.Structure):
 class fg_counters(C.Structure):
     _fields_ = [("scaffold_evals", C.c_uint64), ("harvest_evals", C.c_uint64),
                 ("prune_evals", C.c_uint64), ("expansions", C.c_uint64),
-                ("finalize_evals", C.c_uint64), ("spilled_queries", C.c_uint64)]
+                ("finalize_evals", C.c_uint64), ("spilled_queries", C.c_uint64),
+                ("screen_rejected", C.c_uint64)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -60,14 +64,14 @@ class fg_counters(C.Structure):
 
 class fg_timings(C.Structure):
     _fields_ = [("scaffold_ms", C.c_float), ("harvest_ms", C.c_float),
-                ("merge_ms", C.c_float), ("finalize_ms", C.c_float),
+                ("merge_ms", C.c_float), ("finalize_ms", C.c_float), ("screen_ms", C.c_float),
                 ("block_harvest_ms", C.c_float * 64), ("block_evals", C.c_uint64 * 64),
                 ("nblocks", C.c_uint32)]
 
     def as_dict(self):
         nb = int(self.nblocks)
         return dict(scaffold_ms=self.scaffold_ms, harvest_ms=self.harvest_ms,
-                    merge_ms=self.merge_ms, finalize_ms=self.finalize_ms,
+                    merge_ms=self.merge_ms, finalize_ms=self.finalize_ms, screen_ms=self.screen_ms,
                     block_harvest_ms=list(self.block_harvest_ms)[:nb],
                     block_evals=[int(v) for v in list(self.block_evals)[:nb]])
 
@@ -86,6 +90,8 @@ _SIGS = {
     "fg_search": (C.c_int, [P, P, P, C.c_int64, C.c_uint32, C.c_uint32, P, P, P, P,
                             C.c_size_t, P]),
     "fg_graph_hash": (C.c_int, [P, P, P]),
+    "fg_screen_row_bytes": (C.c_int64, [C.c_int32, C.c_uint32]),
+    "fg_screen_copy": (C.c_int, [P, C.c_uint32, P, P, P, P, P]),
     "fg_leaf_knn_workspace_size": (C.c_size_t, [P]),
     "fg_leaf_knn": (C.c_int, [P, C.c_uint32, C.c_uint32, C.c_int, P, P, P, C.c_size_t, P]),
 }
@@ -147,8 +153,8 @@ def make_data(x: torch.Tensor, metric: str = "l2") -> fg_data:
     return s
 
 
-def make_params(T, ef_h, R, alpha=1.2, B=1, reprune_all=0, beam_table_slots=0) -> fg_params:
-    return fg_params(T, ef_h, R, alpha, B, reprune_all, beam_table_slots, 0)
+def make_params(T, ef_h, R, alpha=1.2, B=1, reprune_all=0, beam_table_slots=0, screen=0) -> fg_params:
+    return fg_params(T, ef_h, R, alpha, B, reprune_all, beam_table_slots, screen)
 
 
 def workspace_size(data: fg_data, params: fg_params) -> int:
@@ -254,6 +260,23 @@ def graph_hash(graph: fg_graph, stream=None) -> int:
     h = C.c_uint64(0)
     _check(lib().fg_graph_hash(C.byref(graph), _stream(stream), C.byref(h)))
     return int(h.value)
+
+
+def screen_copy(data: fg_data, screen: int, stream=None):
+    """The narrow copy of the rows a screened harvest reads: returns
+    (codes uint8 [n, row_bytes], err [n], norm [n], sinv [n]) on the data's
+    device."""
+    rb = int(lib().fg_screen_row_bytes(data.d, screen))
+    if rb <= 0:
+        raise FgError(FG_EINVAL, "bad screen kind or d")
+    dev = data._keep[0].device
+    xs = torch.zeros(data.n, rb, dtype=torch.uint8, device=dev)
+    err = torch.empty(data.n, dtype=torch.float32, device=dev)
+    nrm = torch.empty(data.n, dtype=torch.float32, device=dev)
+    sinv = torch.empty(data.n, dtype=torch.float32, device=dev)
+    _check(lib().fg_screen_copy(C.byref(data), screen, _ptr(xs), _ptr(err), _ptr(nrm), _ptr(sinv),
+                                _stream(stream)))
+    return xs, err, nrm, sinv
 
 
 def leaf_knn(data: fg_data, leaf_size: int, R: int, use_bf16: bool, out_ids, out_d,

@@ -1,0 +1,134 @@
+"""The screening margin (Sec. 5.3's narrow rows, rounding-error analysis in
+the standard model, unit roundoff 2^-24) against the oracle's exact distance
+in the declared float32 order: for random and adversarial pairs, the exact
+distance is never below the screened value minus the margin.  The margin is
+restated here from its derivation (the kernel uses twice this value)."""
+import numpy as np
+import pytest
+import torch
+
+U = 2.0 ** -24
+
+
+def margin(dt, d, E, np_, nu, metric):
+    gs = (d + 12) * U / (1 - (d + 12) * U)
+    gc = (d // 16 + 8) * U / (1 - (d // 16 + 8) * U)
+    if metric == "l2":
+        dd = max(dt, 0.0)
+        A = np.sqrt(dd / (1 - gs)) * (1 + 4 * U)
+        return (gs + gc) * dd + 2 * A * E
+    pu = np_ * (nu + E)
+    return np_ * E + (gs + gc) * pu + 4 * U * (1 + pu)
+
+
+def bf16_back(u):
+    return torch.from_numpy(u).bfloat16().float().numpy()
+
+
+def fp8_back(u):
+    """Nearest-even e4m3 (OCP) of u * 2^k, read back as value * 2^-k."""
+    vals = []
+    for c in range(256):
+        s_, e, m = c >> 7, (c >> 3) & 15, c & 7
+        if e == 15 and m == 7:
+            continue
+        v = m * 2.0 ** -9 if e == 0 else (1 + m / 8) * 2.0 ** (e - 7)
+        vals.append((-v if s_ else v, c))
+    vals.sort()
+    grid = np.array([v for v, _ in vals])
+    mx = np.abs(u.astype(np.float64)).max()
+    k = 0 if mx == 0 else int(np.floor(np.log2(448.0 / mx)))
+    while mx and np.ldexp(mx, k) > 448.0:
+        k -= 1
+    x = u.astype(np.float64) * 2.0 ** k
+    idx = np.abs(x[:, None] - grid[None, :]).argmin(1)
+    return (grid[idx] * 2.0 ** -k).astype(np.float32)
+
+
+def screened(p, ub, metric, mode):
+    """Screened value in float32, several summation orders."""
+    if metric == "l2":
+        t = (p.astype(np.float32) - ub.astype(np.float32)).astype(np.float32)
+        terms = (t * t).astype(np.float32)
+    else:
+        terms = (p.astype(np.float32) * ub.astype(np.float32)).astype(np.float32)
+    if mode == "seq":
+        acc = np.float32(0)
+        for v in terms:
+            acc = np.float32(acc + v)
+    elif mode == "rev":
+        acc = np.float32(0)
+        for v in terms[::-1]:
+            acc = np.float32(acc + v)
+    else:  # pairwise
+        a = terms.copy()
+        while a.size > 1:
+            if a.size % 2:
+                a = np.append(a, np.float32(0))
+            a = (a[0::2] + a[1::2]).astype(np.float32)
+        acc = a[0]
+    if metric == "cosine":
+        acc = np.float32(np.float32(1) - acc)
+    return float(acc)
+
+
+def pairs(metric, rng, d):
+    out = []
+    for _ in range(150):
+        scale = np.exp(rng.uniform(-4, 4))
+        p = (rng.standard_normal(d) * scale).astype(np.float32)
+        u = (p + rng.standard_normal(d) * scale * np.exp(rng.uniform(-8, 1))).astype(np.float32)
+        out.append((p, u))
+    # adversarial: identical rows, rows differing in one element by one ulp,
+    # huge norms with tiny differences, mixed magnitudes, bfloat16 ties
+    p = (rng.standard_normal(d) * 1e4).astype(np.float32)
+    out.append((p, p.copy()))
+    u = p.copy()
+    u[3] = np.nextafter(u[3], np.float32(np.inf))
+    out.append((p, u))
+    out.append((p, (p + 1e-2).astype(np.float32)))
+    m = (rng.standard_normal(d) * np.logspace(-20, 5, d)).astype(np.float32)
+    out.append((m, (m * 1.001).astype(np.float32)))
+    t = ((rng.standard_normal(d).astype(np.float32).view(np.uint32) & 0xFFFF0000) | 0x8000).view(np.float32)
+    out.append((t, t.copy()))
+    if metric == "cosine":
+        out = [(p / np.linalg.norm(p.astype(np.float64)), u / np.linalg.norm(u.astype(np.float64)))
+               for p, u in out if np.linalg.norm(p) > 0 and np.linalg.norm(u) > 0]
+        out = [(p.astype(np.float32), u.astype(np.float32)) for p, u in out]
+    return out
+
+
+@pytest.mark.parametrize("metric", ["l2", "cosine"])
+@pytest.mark.parametrize("kind", ["bf16", "fp8"])
+@pytest.mark.parametrize("d", [68, 100, 960])
+def test_margin_bounds_exact_distance(fgo, metric, kind, d):
+    rng = np.random.default_rng(d * 3 + (kind == "fp8") + 7 * (metric == "cosine"))
+    worst = 0.0
+    for p, u in pairs(metric, rng, d):
+        ub = bf16_back(u) if kind == "bf16" else fp8_back(u)
+        E = np.sqrt(((ub.astype(np.float64) - u.astype(np.float64)) ** 2).sum())
+        np_ = np.sqrt((p.astype(np.float64) ** 2).sum())
+        nu = np.sqrt((u.astype(np.float64) ** 2).sum())
+        D = fgo.Data(np.stack([p, u]), metric=metric)
+        exact = float(fgo.dist(D, 0, 1))
+        for mode in ("seq", "rev", "pair"):
+            dt = screened(p, ub, metric, mode)
+            eps = margin(dt, d, E, np_, nu, metric)
+            assert exact >= dt - eps, (mode, exact, dt, eps)
+            if eps > 0:
+                worst = max(worst, (dt - exact) / eps)
+    assert worst <= 1.0
+
+
+def test_margin_is_not_vacuous_on_neighbours(fgo):
+    """On clustered rows the bfloat16 margin is a few percent of a typical
+    neighbour distance, so the screen can reject."""
+    from paper_2609_30493_amd import datagen as gen
+    x = gen.powerlaw_f32(64, 960, 4, 3)
+    rel = []
+    for i in range(1, 64):
+        ub = bf16_back(x[i])
+        E = np.sqrt(((ub.astype(np.float64) - x[i].astype(np.float64)) ** 2).sum())
+        dt = screened(x[0], ub, "l2", "pair")
+        rel.append(margin(dt, 960, E, 0, 0, "l2") / dt)
+    assert np.median(rel) < 0.05
