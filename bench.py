@@ -152,10 +152,209 @@ def dsweep(args):
     print(json.dumps({"mode": "dsweep", "n": n, "rows": out, "loglog_exponents": fit}), flush=True)
 
 
+def ground_truth_f32(xd: torch.Tensor, qd: torch.Tensor, k: int, metric: str):
+    """Exact k-NN distances in float64 (brute force on the device)."""
+    x64 = xd.double()
+    xn = (x64 * x64).sum(1)
+    out = []
+    for s in range(0, qd.shape[0], 128):
+        q = qd[s:s + 128].double()
+        ip = q @ x64.T
+        d = 1.0 - ip if metric == "cosine" else (q * q).sum(1)[:, None] + xn[None, :] - 2.0 * ip
+        out.append(torch.topk(d, k, dim=1, largest=False).values)
+    return torch.cat(out)
+
+
+def recall_ladder_f32(data, G, ws, qd, true_d, k=10, target=0.95):
+    """Tie-aware recall@k: a returned point counts when its distance is
+    within the true k-th distance (float64 brute force) up to float32
+    rounding of the declared order."""
+    res = []
+    nq = qd.shape[0]
+    kth = true_d[:, -1:]
+    tol = 1e-5 * np.abs(kth) + 1e-6
+    for L in (10, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512):
+        oi = torch.empty(nq, k, dtype=torch.int32, device="cuda")
+        od = torch.empty(nq, k, dtype=torch.float32, device="cuda")
+        oe = torch.empty(nq, dtype=torch.int32, device="cuda")
+        F.search(data, G, qd, k, L, oi, od, oe, ws)
+        torch.cuda.synchronize()
+        found = od.cpu().numpy().astype(np.float64)
+        rec = float(np.mean(found <= kth + tol))
+        res.append(dict(L=L, recall=rec, evals_per_query=float(oe.cpu().numpy().mean())))
+        if rec >= target:
+            break
+    return res
+
+
+def hodges_lehmann(logr: np.ndarray) -> float:
+    w = [(logr[i] + logr[j]) / 2 for i in range(len(logr)) for j in range(i, len(logr))]
+    return float(np.exp(np.median(w)))
+
+
+def screen_compare(args):
+    """Mixed precision against float32 (paired protocol): whole builds of
+    the same workload plain, bf16-screened and fp8-screened, in a seeded
+    random order within each repetition; the graph hash must be identical
+    on every run.  Ratio = plain time / screened time; Hodges-Lehmann
+    estimate over repetitions and the exact Wilcoxon signed-rank p."""
+    from scipy import stats
+    rows = []
+    names = {"cfg3": gen.CFG3, "cfg4": gen.CFG4}
+    for key in args.workloads.split(","):
+        w = names[key]
+        n = args.n or w.n
+        log(f"[screen] {key}: generating {n} x {w.d} rows ({w.recipe})")
+        x = gen.workload_data(w, n)
+        xd = torch.from_numpy(x).cuda()
+        metric = "cosine" if w.metric == "cosine" else "l2"
+        data = F.make_data(xd, metric)
+        forms = (F.SCREEN_NONE, F.SCREEN_BF16, F.SCREEN_FP8E4M3)
+        params = {f: F.make_params(w.T, w.ef_h, w.R, w.alpha, w.B, screen=f) for f in forms}
+        ws = F.alloc_workspace(data, params[F.SCREEN_BF16])  # the largest of the three layouts
+        G = F.make_graph(*(torch.full(sh, -1, dtype=torch.int32, device="cuda")
+                           for sh in ((n, w.R), (n,), (n,), (w.T,))), w.T)
+        hashes = {}
+        for f in forms:  # warm-up: one build per form
+            c, t = F.build_graph(data, w.build_seed, params[f], G, ws, timings=True)
+            hashes[f] = F.graph_hash(G)
+            log(f"[screen] warm-up form {f}: harvest {t['harvest_ms']:.0f} ms, rejected "
+                f"{c['screen_rejected']} of {c['harvest_evals']}")
+        assert len(set(hashes.values())) == 1, hashes
+        rng = np.random.default_rng(20260)
+        res = {f: [] for f in forms}
+        for rep in range(args.reps):
+            for f in rng.permutation(len(forms)):
+                f = forms[f]
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                c, t = F.build_graph(data, w.build_seed, params[f], G, ws, timings=True)
+                wall = time.perf_counter() - t0
+                assert F.graph_hash(G) == hashes[F.SCREEN_NONE]
+                res[f].append(dict(harvest_ms=t["harvest_ms"], build_s=wall, screen_ms=t["screen_ms"],
+                                   evals=c["harvest_evals"], rejected=c["screen_rejected"]))
+                log(f"[screen] rep {rep} form {f}: harvest {t['harvest_ms']:.0f} ms build {wall:.2f} s")
+        row = {"workload": w.name, "n": n, "d": w.d, "metric": metric, "graph_hash": f"{hashes[0]:#018x}",
+               "harvest_evals": res[0][0]["evals"], "forms": {}}
+        base_h = np.array([r["harvest_ms"] for r in res[0]])
+        base_b = np.array([r["build_s"] for r in res[0]])
+        row_bytes = 4 * w.d
+        for f, name in zip(forms, ("fp32", "bf16", "fp8e4m3")):
+            h = np.array([r["harvest_ms"] for r in res[f]])
+            b = np.array([r["build_s"] for r in res[f]])
+            ev = res[f][0]["evals"]
+            rej = res[f][0]["rejected"]
+            narrow = {0: 0, 1: 2 * w.d, 2: w.d}[f]
+            e = {"harvest_ms_median": float(np.median(h)), "build_s_median": float(np.median(b)),
+                 "harvest_evals_per_s": float(ev / (np.median(h) / 1e3)),
+                 "screen_rejected_frac": rej / ev,
+                 "bytes_per_eval": narrow + (1 - rej / ev) * row_bytes if f else row_bytes,
+                 "screen_copy_ms": float(np.median([r["screen_ms"] for r in res[f]]))}
+            if f:
+                lr_h, lr_b = np.log(base_h / h), np.log(base_b / b)
+                e["harvest_speedup_hl"] = hodges_lehmann(lr_h)
+                e["build_speedup_hl"] = hodges_lehmann(lr_b)
+                if len(h) >= 2:
+                    e["wilcoxon_p_harvest"] = float(stats.wilcoxon(lr_h, method="exact").pvalue)
+                    e["wilcoxon_p_build"] = float(stats.wilcoxon(lr_b, method="exact").pvalue)
+            row["forms"][name] = e
+        if not args.no_recall:
+            qd = torch.from_numpy(gen.workload_queries(w, min(w.nq, 1000))).cuda()
+            true_d = ground_truth_f32(xd, qd, 10, metric).cpu().numpy()
+            F.build_graph(data, w.build_seed, params[0], G, ws)
+            row["recall_ladder"] = recall_ladder_f32(data, G, ws, qd, true_d)
+        log(f"[screen] {json.dumps(row)}")
+        rows.append(row)
+        del ws, G, xd, data
+        torch.cuda.empty_cache()
+    print(json.dumps({"mode": "screen", "reps": args.reps, "rows": rows}), flush=True)
+
+
+def batched_compare(args):
+    """Batched form (cfg5): 64 uneven instances built together -- eager, and
+    with the blocks captured in one HIP graph -- against 64 sequential
+    build_graph calls, paired repetitions in seeded random order; every
+    instance's graph hash must equal its sequential build's."""
+    from scipy import stats
+    count = args.instances
+    insts = gen.batched_instances(count=count, scale=args.scale)
+    ntot = sum(i["x"].shape[0] for i in insts)
+    log(f"[batched] {count} instances, {ntot} points in all")
+    datas, params, graphs = [], [], []
+
+    def u32(*shape):
+        return torch.full(shape, -1, dtype=torch.int32, device="cuda")
+
+    for i in insts:
+        n = i["x"].shape[0]
+        datas.append(F.make_data(torch.from_numpy(i["x"]).cuda()))
+        params.append(F.make_params(i["T"], i["ef_h"], i["R"], i["alpha"], i["B"]))
+        graphs.append(F.make_graph(u32(n, i["R"]), u32(n), u32(n), u32(i["T"]), i["T"]))
+    seeds = [i["seed"] for i in insts]
+    big = max(range(count), key=lambda k: insts[k]["x"].shape[0])
+    ws_seq = F.alloc_workspace(datas[big], F.make_params(8, 128, 32, 1.2, 8))
+
+    def sequential():
+        ev = 0
+        for k in range(count):
+            c, _ = F.build_graph(datas[k], seeds[k], params[k], graphs[k], ws_seq)
+            ev += c["harvest_evals"]
+        return ev
+
+    ws_b = None
+
+    def batched(use_graph):
+        nonlocal ws_b
+        c, ws_b = F.build_graph_batched(datas, params, seeds, graphs, ws=ws_b, use_hipgraph=use_graph)
+        return c["harvest_evals"]
+
+    runs = {"sequential": sequential, "batched": lambda: batched(False), "batched_hipgraph": lambda: batched(True)}
+    # warm-up and hash check
+    sequential()
+    want = [F.graph_hash(g) for g in graphs]
+    for name in ("batched", "batched_hipgraph"):
+        runs[name]()
+        got = [F.graph_hash(g) for g in graphs]
+        assert got == want, name
+    rng = np.random.default_rng(5150)
+    times = {k: [] for k in runs}
+    evals = {}
+    for rep in range(args.reps):
+        for j in rng.permutation(len(runs)):
+            name = list(runs)[j]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            evals[name] = runs[name]()
+            torch.cuda.synchronize()
+            times[name].append(time.perf_counter() - t0)
+            log(f"[batched] rep {rep} {name}: {times[name][-1]:.3f} s")
+    got = [F.graph_hash(g) for g in graphs]
+    assert got == want
+    seq = np.array(times["sequential"])
+    out = {"mode": "batched", "instances": count, "points": ntot, "reps": args.reps,
+           "harvest_evals": evals["sequential"], "forms": {}}
+    for name in runs:
+        t = np.array(times[name])
+        e = {"build_s_median": float(np.median(t)), "points_per_s": ntot / float(np.median(t))}
+        if name != "sequential":
+            lr = np.log(seq / t)
+            e["speedup_hl"] = hodges_lehmann(lr)
+            if len(t) >= 2:
+                e["wilcoxon_p"] = float(stats.wilcoxon(lr, method="exact").pvalue)
+        out["forms"][name] = e
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", default="build", choices=("build", "dsweep"),
-                    help="build: the benchmark line (default); dsweep: wall vs dimension")
+    ap.add_argument("--mode", default="build", choices=("build", "dsweep", "screen", "batched"),
+                    help="build: the benchmark line (default); dsweep: wall vs dimension; "
+                         "screen: bf16 / fp8 screened builds against float32; "
+                         "batched: 64 instances built together against sequential builds")
+    ap.add_argument("--instances", type=int, default=64, help="batched mode: instance count")
+    ap.add_argument("--scale", type=float, default=1.0, help="batched mode: shrink every instance's n")
+    ap.add_argument("--workloads", default="cfg3,cfg4", help="screen mode: cfg3, cfg4 or both")
+    ap.add_argument("--reps", type=int, default=3, help="screen mode: paired repetitions")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
@@ -175,6 +374,10 @@ def main():
         sys.exit(2)
     if args.mode == "dsweep":
         return dsweep(args)
+    if args.mode == "screen":
+        return screen_compare(args)
+    if args.mode == "batched":
+        return batched_compare(args)
 
     w = gen.CFG2
     n = args.n or w.n

@@ -210,6 +210,27 @@ fg_status fg_build_graph(const fg_data* data, uint64_t seed,
                          size_t ws_bytes, void* stream, fg_counters* counters,
                          fg_timings* timings);
 
+/* Batched builds: count independent instances, each exactly the graph
+ * fg_build_graph would give it (same hash), built together so that one
+ * harvest launch per block serves every instance (uneven beam lengths and
+ * small instances keep the whole device busy).  Instances share dtype,
+ * metric, T, R, alpha, B, reprune_all and beam_table_slots; n, d, ef_h and
+ * the seed may differ; screen must be FG_SCREEN_NONE.  outs[i] is shaped
+ * like instance i.  With use_hipgraph != 0 the B harvests and merges are
+ * captured into one HIP graph (on a stream of the library's own, ordered
+ * after and before `stream`) and replayed once; merges then finish rows
+ * with more than 2048 additions on the device alone.  Synchronises
+ * `stream`.  The workspace must hold
+ * fg_batched_workspace_size() bytes (0 = invalid arguments). */
+size_t fg_batched_workspace_size(const fg_data* const* data,
+                                 const fg_params* const* params, uint32_t count);
+fg_status fg_build_graph_batched(const fg_data* const* data,
+                                 const fg_params* const* params,
+                                 const uint64_t* seeds, uint32_t count,
+                                 fg_graph* const* outs, void* ws_dev,
+                                 size_t ws_bytes, void* stream,
+                                 int use_hipgraph, fg_counters* counters);
+
 /* Query search (Sec. 2, "quality"): beam of width L over G u spine from the
  * roots for nq query rows (queries_dev, contiguous rows of d elements of the
  * data's dtype); writes the first k entries per query: ids (nq x k), their

@@ -56,7 +56,7 @@ def build(jobs: int | None = None, defines=(), out: str | None = None) -> str:
         objs = list(ex.map(lambda src: _compile(src, defines, tag), srcs))
     target = out or OUT
     tmp = target + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,--no-undefined", "-o", tmp, *objs]
     subprocess.run(cmd, check=True)
     os.replace(tmp, target)
     return target

@@ -189,17 +189,27 @@ char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
 
 // Launch the harvest of block b.  The spill bitsets must be zero on entry
 // (they are left zero on exit).
+// Instances of a batched build sharing one id space (see fg_build_graph_batched).
+struct BatchInfo {
+  const uint16_t* inst_of;
+  const uint32_t* inst_roots;
+  const int* inst_ef;
+  int ef_max;
+};
+
 fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* ids,
                          const uint32_t* roots, const fg_params* P, uint32_t b, uint32_t* rows,
-                         uint32_t* cnt, void* ws, const WsMap& m, hipStream_t st) {
+                         uint32_t* cnt, void* ws, const WsMap& m, hipStream_t st,
+                         const BatchInfo* bi = nullptr) {
   const uint32_t Be = b_eff(P);
   int64_t nitems = s.n > (int64_t)b ? (s.n - (int64_t)b + Be - 1) / Be : 0;
   Ctl* ctl = reinterpret_cast<Ctl*>(at(ws, m.ctl));
   FG_HIP(fill_u64(reinterpret_cast<uint64_t*>(&ctl->queue), 0, 1, st));
   if (nitems == 0) return FG_OK;
-  const int hslots = beam_table_slots((int)P->ef_h, false, table_request(P));
+  const int ef = bi ? bi->ef_max : (int)P->ef_h;
+  const int hslots = beam_table_slots(ef, false, table_request(P));
   const int screen = (int)P->screen;
-  int grid = beam_grid(s, (int)P->ef_h, false, hslots, screen);
+  int grid = beam_grid(s, ef, false, hslots, screen);
   if (grid <= 0) return set_error("no beam kernel for this row size / ef_h"), FG_EUNSUPPORTED;
   BeamArgs a{};
   a.x = s.x;
@@ -210,7 +220,7 @@ fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* id
   a.ids = ids;
   a.roots = roots;
   a.T = (int)P->T;
-  a.ef = (int)P->ef_h;
+  a.ef = ef;
   a.R = (int)P->R;
   a.alpha = P->alpha;
   a.b = b;
@@ -228,6 +238,11 @@ fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* id
   a.counters = ctl->counters;
   a.status = &ctl->status;
   a.d = s.d;
+  if (bi) {
+    a.inst_of = bi->inst_of;
+    a.inst_roots = bi->inst_roots;
+    a.inst_ef = bi->inst_ef;
+  }
   if (screen) {
     a.xs = reinterpret_cast<const uint8_t*>(at(ws, m.xs));
     a.xs_stride = m.xs_stride;
@@ -260,13 +275,21 @@ fg_status read_ctl(void* ws, const WsMap& m, hipStream_t st, Ctl* out) {
 
 // Per-row union of sorted old rows with unsorted additions (see merge_rows);
 // rows with too many additions for one wave's LDS take the global path.
+//
+// device_only: nothing waits for the host (for captured streams); big rows
+// take the device-side path.
 fg_status merge_rows_all(int64_t n, const uint64_t* off0, const uint32_t* ids0, const uint64_t* aoff,
                          const uint32_t* addbuf, uint32_t* tmp, uint32_t* newlen, void* ws, const WsMap& m,
-                         hipStream_t st) {
+                         hipStream_t st, bool device_only = false) {
   Ctl* ctl = reinterpret_cast<Ctl*>(at(ws, m.ctl));
   uint32_t* big = reinterpret_cast<uint32_t*>(at(ws, m.big));
   FG_HIP(fill_u32(&ctl->nbig, 0, 1, st));
   FG_HIP(merge_rows(n, off0, ids0, aoff, addbuf, tmp, newlen, big, &ctl->nbig, st));
+  if (device_only) {
+    FG_HIP(merge_big_rows_dev(big, &ctl->nbig, off0, ids0, aoff, addbuf,
+                              reinterpret_cast<uint32_t*>(at(ws, m.keys2)), tmp, newlen, st));
+    return FG_OK;
+  }
   uint32_t nbig = 0;
   FG_HIP(hipMemcpyAsync(&nbig, &ctl->nbig, 4, hipMemcpyDeviceToHost, st));
   FG_HIP(hipStreamSynchronize(st));
@@ -283,7 +306,8 @@ fg_status merge_rows_all(int64_t n, const uint64_t* off0, const uint32_t* ids0, 
 // ids1; the caller guarantees the capacity.
 fg_status merge_launch(int64_t n, const uint64_t* off0, const uint32_t* ids0, const uint32_t* rows,
                        const uint32_t* cnt, int R, uint32_t b, uint32_t Be, uint64_t* off1,
-                       uint32_t* ids1, void* ws, const WsMap& m, hipStream_t st) {
+                       uint32_t* ids1, void* ws, const WsMap& m, hipStream_t st,
+                       bool device_only = false) {
   int64_t nitems = n > (int64_t)b ? (n - (int64_t)b + Be - 1) / Be : 0;
   uint32_t* deg = reinterpret_cast<uint32_t*>(at(ws, m.deg));
   uint32_t* cursor = reinterpret_cast<uint32_t*>(at(ws, m.cursor));
@@ -298,7 +322,7 @@ fg_status merge_launch(int64_t n, const uint64_t* off0, const uint32_t* ids0, co
   FG_HIP(exclusive_scan_u32_u64(deg, aoff, n, scan, st));
   FG_HIP(fill_u32(cursor, 0, n, st));
   FG_HIP(edges_scatter(n, rows, cnt, R, b, Be, nitems, true, true, aoff, cursor, addbuf, st));
-  fg_status r = merge_rows_all(n, off0, ids0, aoff, addbuf, tmp, newlen, ws, m, st);
+  fg_status r = merge_rows_all(n, off0, ids0, aoff, addbuf, tmp, newlen, ws, m, st, device_only);
   if (r) return r;
   FG_HIP(exclusive_scan_u32_u64(newlen, off1, n, scan, st));
   FG_HIP(compact_rows(n, off0, aoff, tmp, off1, ids1, st));
@@ -818,6 +842,261 @@ fg_status fg_build_graph(const fg_data* data, uint64_t seed, const fg_params* pa
   }
   cleanup();
 #undef FG_TRY
+  return status_error(c.status);
+}
+
+// ---------------------------------------------------------------- batched
+// Many independent instances in one id space: instance i owns ids
+// [off_i, off_i + n_i) with off_i a multiple of B, so a point's block is the
+// same as in its own build; rows are copied into one matrix whose stride fits
+// the widest instance, zero-padded (zero chunks add exactly nothing in the
+// declared order, so every distance is that of the instance alone).  The
+// scaffold is built per instance; each block is one harvest launch over all
+// instances (per-point instance, roots and beam width) and one merge over the
+// whole id space; finalize runs once; each instance's graph is copied back
+// in its own ids.
+namespace {
+
+struct BatchPlan {
+  Shape s;
+  fg_params P;
+  int64_t N = 0, stride = 0;
+  int ef_max = 0;
+  std::vector<int64_t> off;
+  WsMap m;
+  size_t x_at = 0, inst_at = 0, roots_at = 0, ef_at = 0, nbrs_at = 0, gcnt_at = 0, tpl_at = 0;
+  size_t total = 0;
+};
+
+bool plan_batch(const fg_data* const* data, const fg_params* const* params, uint32_t count, BatchPlan* bp) {
+  if (!data || !params || count < 1 || count > 65535)
+    return set_error("need 1 <= count <= 65535 instances and data/params arrays"), false;
+  int64_t nmax = 0;
+  int dk = -1;
+  for (uint32_t i = 0; i < count; i++) {
+    Shape si;
+    if (!data[i] || !params[i]) return set_error("NULL data or params entry"), false;
+    if (!make_shape(data[i], &si)) return false;
+    if (!check_params(params[i], si.n)) return false;
+    if (params[i]->screen) return set_error("batched builds do not screen"), false;
+    const fg_params* a = params[0];
+    const fg_params* b = params[i];
+    if (b->T != a->T || b->R != a->R || b->alpha != a->alpha || b_eff(b) != b_eff(a) ||
+        b->reprune_all != a->reprune_all || b->beam_table_slots != a->beam_table_slots)
+      return set_error("batched instances must share T, R, alpha, B, reprune_all and beam_table_slots"), false;
+    if (dk >= 0 && si.dk != dk) return set_error("batched instances must share dtype and metric"), false;
+    dk = si.dk;
+    const int64_t rb = (int64_t)si.Q * 16;
+    bp->stride = rb > bp->stride ? rb : bp->stride;
+    bp->ef_max = (int)b->ef_h > bp->ef_max ? (int)b->ef_h : bp->ef_max;
+    nmax = si.n > nmax ? si.n : nmax;
+  }
+  const int64_t Be = b_eff(params[0]);
+  bp->off.assign(count + 1, 0);
+  for (uint32_t i = 0; i < count; i++) bp->off[i + 1] = bp->off[i] + (data[i]->n + Be - 1) / Be * Be;
+  bp->N = bp->off[count];
+  if (bp->N >= (int64_t)0xFFFFFFFFu) return set_error("too many points in the batch"), false;
+  bp->P = *params[0];
+  bp->P.ef_h = (uint32_t)bp->ef_max;
+  bp->s.x = nullptr;
+  bp->s.stride = bp->stride;
+  bp->s.n = bp->N;
+  bp->s.dk = dk;
+  bp->s.Q = (int)(bp->stride / 16);
+  bp->s.d = dk == U8L2 ? (int)bp->stride : (int)(bp->stride / 4);
+  bp->m = ws_map(bp->N, &bp->P);
+  size_t o = bp->m.total;
+  auto take = [&](size_t bytes) {
+    size_t at_ = o;
+    o += align256(bytes);
+    return at_;
+  };
+  const uint64_t N = (uint64_t)bp->N, T = bp->P.T, R = bp->P.R;
+  bp->x_at = take(N * (uint64_t)bp->stride);
+  bp->inst_at = take(N * 2);
+  bp->roots_at = take((uint64_t)count * T * 4);
+  bp->ef_at = take((uint64_t)count * 4);
+  bp->nbrs_at = take(N * R * 4);
+  bp->gcnt_at = take(N * 4);
+  bp->tpl_at = take(T * (uint64_t)nmax * 4);
+  bp->total = o;
+  return true;
+}
+
+}  // namespace
+
+size_t fg_batched_workspace_size(const fg_data* const* data, const fg_params* const* params, uint32_t count) {
+  BatchPlan bp;
+  if (!plan_batch(data, params, count, &bp)) return 0;
+  return bp.total;
+}
+
+fg_status fg_build_graph_batched(const fg_data* const* data, const fg_params* const* params,
+                                 const uint64_t* seeds, uint32_t count, fg_graph* const* outs, void* ws_dev,
+                                 size_t ws_bytes, void* stream, int use_hipgraph, fg_counters* counters) {
+  BatchPlan bp;
+  if (!plan_batch(data, params, count, &bp)) return FG_EINVAL;
+  if (!seeds || !outs) return set_error("seeds and outs are required"), FG_EINVAL;
+  const uint32_t T = bp.P.T, R = bp.P.R;
+  for (uint32_t i = 0; i < count; i++) {
+    const fg_graph* g = outs[i];
+    if (!g || !g->nbrs_dev || !g->cnt_dev || !g->spine_parent_dev || !g->roots_dev)
+      return set_error("every array of every output graph is required"), FG_EINVAL;
+    if (g->n != data[i]->n || g->R != R || g->T != T)
+      return set_error("an output graph's shape does not match its instance"), FG_EINVAL;
+  }
+  if (!ws_dev || reinterpret_cast<uintptr_t>(ws_dev) % 256) return set_error("workspace must be 256-byte aligned"), FG_EINVAL;
+  if (ws_bytes < bp.total) return set_error("workspace too small (see fg_batched_workspace_size)"), FG_ENOMEM;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const WsMap& m = bp.m;
+  const int64_t N = bp.N;
+  const uint32_t Be = b_eff(&bp.P);
+  uint8_t* X = reinterpret_cast<uint8_t*>(at(ws_dev, bp.x_at));
+  bp.s.x = X;
+  uint16_t* inst_of = reinterpret_cast<uint16_t*>(at(ws_dev, bp.inst_at));
+  uint32_t* inst_roots = reinterpret_cast<uint32_t*>(at(ws_dev, bp.roots_at));
+  int* inst_ef = reinterpret_cast<int*>(at(ws_dev, bp.ef_at));
+  uint32_t* gnbrs = reinterpret_cast<uint32_t*>(at(ws_dev, bp.nbrs_at));
+  uint32_t* gcnt = reinterpret_cast<uint32_t*>(at(ws_dev, bp.gcnt_at));
+  uint32_t* tpl = reinterpret_cast<uint32_t*>(at(ws_dev, bp.tpl_at));
+  uint32_t* tparent = reinterpret_cast<uint32_t*>(at(ws_dev, m.tparent));
+  uint32_t* rdev = reinterpret_cast<uint32_t*>(at(ws_dev, m.roots));
+  uint64_t* off[2] = {reinterpret_cast<uint64_t*>(at(ws_dev, m.off[0])),
+                      reinterpret_cast<uint64_t*>(at(ws_dev, m.off[1]))};
+  uint32_t* ids[2] = {reinterpret_cast<uint32_t*>(at(ws_dev, m.ids[0])),
+                      reinterpret_cast<uint32_t*>(at(ws_dev, m.ids[1]))};
+  uint32_t* rows = reinterpret_cast<uint32_t*>(at(ws_dev, m.rows));
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(at(ws_dev, m.cnt));
+
+  // The shared matrix, the per-point instance and the per-instance tables.
+  FG_HIP(fill_u32(reinterpret_cast<uint32_t*>(X), 0, N * bp.stride / 4, st));
+  std::vector<uint16_t> hinst((size_t)N, 0xFFFFu);
+  std::vector<uint32_t> hroots_all((size_t)count * T), hroots_local((size_t)count * T);
+  std::vector<int> hef(count);
+  for (uint32_t i = 0; i < count; i++) {
+    const fg_data* di = data[i];
+    const int64_t esz = di->dtype == FG_U8 ? 1 : 4;
+    FG_HIP(hipMemcpy2DAsync(X + bp.off[i] * bp.stride, (size_t)bp.stride, di->x_dev, (size_t)di->row_stride_bytes,
+                            (size_t)(di->d * esz), (size_t)di->n, hipMemcpyDeviceToDevice, st));
+    for (int64_t j = 0; j < di->n; j++) hinst[(size_t)(bp.off[i] + j)] = (uint16_t)i;
+    fg_status r = fg_roots(seeds[i], di->n, T, &hroots_local[(size_t)i * T]);
+    if (r) return r;
+    for (uint32_t t = 0; t < T; t++)
+      hroots_all[(size_t)i * T + t] = hroots_local[(size_t)i * T + t] + (uint32_t)bp.off[i];
+    hef[i] = (int)params[i]->ef_h;
+  }
+  FG_HIP(hipMemcpyAsync(inst_of, hinst.data(), hinst.size() * 2, hipMemcpyHostToDevice, st));
+  FG_HIP(hipMemcpyAsync(inst_roots, hroots_all.data(), hroots_all.size() * 4, hipMemcpyHostToDevice, st));
+  FG_HIP(hipMemcpyAsync(inst_ef, hef.data(), hef.size() * 4, hipMemcpyHostToDevice, st));
+  fg_status r = reset_ctl(ws_dev, m, st);
+  if (r) return r;
+  FG_HIP(hipStreamSynchronize(st));  // the host tables above must outlive their copies
+
+  // Scaffold: T trees per instance, parents moved into the shared id space.
+  FG_HIP(fill_u32(tparent, FG_NONE, (int64_t)T * N, st));
+  unsigned long long sat_evals = 0;
+  for (uint32_t i = 0; i < count; i++) {
+    Shape si = bp.s;
+    si.x = X + bp.off[i] * bp.stride;
+    si.n = data[i]->n;
+    SatWs sw;
+    sat_workspace_bytes(si.n, T, &sw);
+    FG_HIP(hipMemcpyAsync(rdev, &hroots_local[(size_t)i * T], T * 4, hipMemcpyHostToDevice, st));
+    unsigned long long ev = 0;
+    int status = 0;
+    FG_HIP(sat_build(si, rdev, T, tpl, at(ws_dev, m.sat), sw, st, &ev, &status));
+    if (status) return status_error(status);
+    sat_evals += ev;
+    FG_HIP(scatter_parents(tpl, si.n, T, N, bp.off[i], tparent, st));
+  }
+  r = scaffold_csr_launch(N, T, tparent, off[0], ids[0], ws_dev, m, st);
+  if (r) return r;
+
+  // Blocks.
+  const BatchInfo bi{inst_of, inst_roots, inst_ef, bp.ef_max};
+  auto init_rows = [&](hipStream_t s_) -> fg_status {
+    FG_HIP(fill_u32(rows, FG_NONE, N * (int64_t)R, s_));
+    FG_HIP(fill_u32(cnt, 0, N, s_));
+    FG_HIP(fill_u32(reinterpret_cast<uint32_t*>(at(ws_dev, m.bits)), 0, (int64_t)kMaxWaveSlots * m.spill_words, s_));
+    return FG_OK;
+  };
+  auto blocks = [&](hipStream_t s_, bool device_only) -> fg_status {
+    int cur = 0;
+    for (uint32_t b = 0; b < Be; b++) {
+      fg_status rr = harvest_launch(bp.s, off[cur], ids[cur], inst_roots, &bp.P, b, rows, cnt, ws_dev, m, s_, &bi);
+      if (rr) return rr;
+      if (b + 1 < Be) {
+        rr = merge_launch(N, off[cur], ids[cur], rows, cnt, (int)R, b, Be, off[cur ^ 1], ids[cur ^ 1], ws_dev, m,
+                          s_, device_only);
+        if (rr) return rr;
+        cur ^= 1;
+      }
+    }
+    return FG_OK;
+  };
+  r = init_rows(st);
+  if (r) return r;
+  if (use_hipgraph) {
+    // Capture the blocks on a stream of our own (ordered after and before
+    // the caller's stream) and replay the graph once.
+    hipStream_t cs = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    auto release = [&]() {  // best effort: the first error is the one reported
+      if (ge) (void)hipGraphExecDestroy(ge);
+      if (g) (void)hipGraphDestroy(g);
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      if (cs) (void)hipStreamDestroy(cs);
+    };
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&e0, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&e1, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(cs, e0, 0);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      release();
+      FG_HIP(e);
+    }
+    fg_status rb = blocks(cs, true);
+    e = hipStreamEndCapture(cs, &g);
+    if (rb) {
+      release();
+      return rb;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(ge, cs);
+    if (e == hipSuccess) e = hipEventRecord(e1, cs);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, e1, 0);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    release();
+    FG_HIP(e);
+  } else {
+    r = blocks(st, false);
+    if (r) return r;
+  }
+
+  // Finalize over the shared id space, then each instance in its own ids.
+  r = finalize_launch(bp.s, rows, cnt, &bp.P, gnbrs, gcnt, ws_dev, m, st);
+  if (r) return r;
+  for (uint32_t i = 0; i < count; i++) {
+    FG_HIP(localize_graph(gnbrs, gcnt, tparent, data[i]->n, (int)R, bp.off[i], outs[i]->nbrs_dev, outs[i]->cnt_dev,
+                          outs[i]->spine_parent_dev, st));
+    FG_HIP(hipMemcpyAsync(outs[i]->roots_dev, &hroots_local[(size_t)i * T], T * 4, hipMemcpyHostToDevice, st));
+  }
+  Ctl c;
+  r = read_ctl(ws_dev, m, st, &c);
+  if (r) return r;
+  if (counters) {
+    counters->scaffold_evals += sat_evals;
+    counters->harvest_evals += c.counters[0];
+    counters->expansions += c.counters[1];
+    counters->prune_evals += c.counters[2];
+    counters->spilled_queries += c.counters[3];
+    counters->finalize_evals += c.fin[0] + c.fin[1];
+  }
   return status_error(c.status);
 }
 

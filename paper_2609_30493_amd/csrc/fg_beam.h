@@ -38,7 +38,15 @@ namespace fg {
 // spent by lane 0 of every wave in each phase of the beam loop, summed over
 // the grid into fg_prof_cycles[].  Absent from normal builds.
 #ifdef FG_PROFILE
-extern __device__ unsigned long long fg_prof_cycles[16];
+// One array per translation unit; each unit exports its own reader.
+static __device__ unsigned long long fg_prof_cycles[16];
+#define FG_PROF_READER(name)                                                               \
+  extern "C" int name(unsigned long long* out16) {                                        \
+    if (hipMemcpyFromSymbol(out16, HIP_SYMBOL(fg::fg_prof_cycles), 16 * 8) != hipSuccess) \
+      return -1;                                                                          \
+    unsigned long long z[16] = {};                                                        \
+    return hipMemcpyToSymbol(HIP_SYMBOL(fg::fg_prof_cycles), z, 16 * 8) == hipSuccess ? 0 : -1; \
+  }
 #define FG_T0() uint64_t fg_t0_ = __builtin_amdgcn_s_memtime()
 #define FG_TICK(slot)                                        \
   do {                                                       \
@@ -102,6 +110,12 @@ struct BeamArgs {
   const float* xs_norm;
   const float* xs_sinv;
   int d;
+  // batched builds: many instances in one id space.  inst_of[p] is p's
+  // instance (0xFFFF: an unused id, skipped), whose T roots are
+  // inst_roots[i*T ..] and beam width inst_ef[i] (<= ef).  NULL otherwise.
+  const uint16_t* inst_of;
+  const uint32_t* inst_roots;
+  const int* inst_ef;
 };
 
 enum ScreenKind { SCR_NONE = 0, SCR_BF16 = 1, SCR_FP8 = 2 };
@@ -376,7 +390,6 @@ __global__ void __launch_bounds__(64) k_beam(BeamArgs A) {
   constexpr uint32_t HMASK = HSLOTS - 1;
   constexpr int HCAP = HSLOTS / 2 - 64;  // load <= 1/2; checked after every 64 insertions
   constexpr int kRB = (NCH >= 16) ? 1 : 16 / NCH;
-  const int ef = A.ef;
   const RowSet X{A.x, A.stride, A.Q};
 
   unsigned long long my_evals = 0, my_exp = 0, my_pe = 0, my_spilled = 0, my_rej = 0;
@@ -392,6 +405,16 @@ __global__ void __launch_bounds__(64) k_beam(BeamArgs A) {
     if ((int64_t)item >= A.nitems) break;
 
     const int64_t p = SEARCH ? (int64_t)item : A.b + (int64_t)item * A.B;
+    int ef = A.ef;
+    const uint32_t* roots = A.roots;
+    if constexpr (!SEARCH) {
+      if (A.inst_of) {
+        const uint32_t inst = A.inst_of[p];
+        if (inst == 0xFFFFu) continue;  // an unused id between instances
+        ef = A.inst_ef[inst];
+        roots = A.inst_roots + (size_t)inst * A.T;
+      }
+    }
     const uint8_t* qrow = SEARCH ? A.queries + (size_t)item * A.qstride : A.x + (size_t)p * A.stride;
     Chunks<L, NCH> qc;
     load_chunks<L, NCH>(qc, qrow, A.Q, g);
@@ -521,7 +544,7 @@ __global__ void __launch_bounds__(64) k_beam(BeamArgs A) {
     };
 
     FG_TICK(6);
-    process(A.roots, A.T);
+    process(roots, A.T);
     for (;;) {
       int first = -1;
       for (int base = 0; base < bsize; base += 64) {

@@ -95,17 +95,9 @@ hipError_t launch_beam(const Shape& s, BeamArgs& a, bool search, int grid, int h
   return hipLaunchKernel(reinterpret_cast<const void*>(k), dim3(grid), dim3(64), args, 0, st);
 }
 
-#ifdef FG_PROFILE
-__device__ unsigned long long fg_prof_cycles[16];
-#endif
-
 }  // namespace fg
 
 #ifdef FG_PROFILE
-// Profiling builds only: read and clear the phase cycle counters.
-extern "C" int fg_prof_read(unsigned long long* out16) {
-  if (hipMemcpyFromSymbol(out16, HIP_SYMBOL(fg::fg_prof_cycles), 16 * 8) != hipSuccess) return -1;
-  unsigned long long z[16] = {};
-  return hipMemcpyToSymbol(HIP_SYMBOL(fg::fg_prof_cycles), z, 16 * 8) == hipSuccess ? 0 : -1;
-}
+// Profiling builds only: read and clear this unit's phase cycle counters.
+FG_PROF_READER(fg_prof_read)
 #endif

@@ -39,3 +39,7 @@ void* pick_screen_fp8(int dk, int Q, int ef, int hslots) {
 }
 
 }  // namespace fg
+
+#ifdef FG_PROFILE
+FG_PROF_READER(fg_prof_read_sfp8)
+#endif

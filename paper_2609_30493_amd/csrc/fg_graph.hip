@@ -210,6 +210,108 @@ __global__ void __launch_bounds__(64) k_merge_rows(int64_t n, const uint64_t* of
   }
 }
 
+// Rows with more than kMergeAddMax additions without the host: workgroups of
+// 1024 threads take the rows listed in big[0..*nbig) in turn.  A row's
+// additions are sorted by a bitonic network in global scratch (row v uses
+// the 2 * a entries at scratch + 2 * addoff[v], enough for the power of two
+// M >= a), reduced in place to the ids that are new (first occurrence, not
+// in the old row), then merged with the old row by co-ranking into the
+// row's upper-bound slot of tmp, as k_merge_rows does.
+__global__ void __launch_bounds__(1024) k_merge_big_dev(const uint32_t* big, const uint32_t* nbig,
+                                                        const uint64_t* off, const uint32_t* ids,
+                                                        const uint64_t* addoff, const uint32_t* addbuf,
+                                                        uint32_t* scratch, uint32_t* tmp, uint32_t* newlen) {
+  __shared__ uint32_t wcount[16];
+  __shared__ uint32_t carry;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nt = blockDim.x;
+  const uint32_t nb = *nbig;
+  for (uint32_t k = blockIdx.x; k < nb; k += gridDim.x) {
+    const uint32_t v = big[k];
+    const uint64_t o0 = off[v];
+    const int64_t o = (int64_t)(off[v + 1] - o0);
+    const uint64_t a0 = addoff[v];
+    const int64_t a = (int64_t)(addoff[v + 1] - a0);
+    int64_t M = 1;
+    while (M < a) M <<= 1;
+    uint32_t* buf = scratch + 2 * a0;
+    for (int64_t i = tid; i < M; i += nt) buf[i] = i < a ? addbuf[a0 + i] : FG_NONE;
+    __syncthreads();
+    for (int64_t kb = 2; kb <= M; kb <<= 1) {
+      for (int64_t jb = kb >> 1; jb > 0; jb >>= 1) {
+        for (int64_t i = tid; i < M; i += nt) {
+          const int64_t ixj = i ^ jb;
+          if (ixj > i) {
+            const uint32_t x0 = buf[i], x1 = buf[ixj];
+            if ((x0 > x1) == ((i & kb) == 0)) {
+              buf[i] = x1;
+              buf[ixj] = x0;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // in-place compaction: every read of a chunk precedes its writes, which
+    // land at or before the chunk; the raw last value of the previous chunk
+    // is carried for the repeat test
+    int64_t u = 0;
+    if (tid == 0) carry = FG_NONE;
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < M; c0 += nt) {
+      const int64_t i = c0 + tid;
+      const uint32_t x = i < M ? buf[i] : FG_NONE;
+      const uint32_t prev = tid == 0 ? carry : (i - 1 < M ? buf[i - 1] : FG_NONE);
+      bool keep = x != FG_NONE && !(i > 0 && prev == x);
+      if (keep) {
+        int64_t lo = 0, hi = o;
+        while (lo < hi) {
+          const int64_t mid = (lo + hi) >> 1;
+          if (ids[o0 + mid] < x) lo = mid + 1;
+          else hi = mid;
+        }
+        keep = !(lo < o && ids[o0 + lo] == x);
+      }
+      const uint64_t m = ballot(keep);
+      if (lane == 0) wcount[wv] = (uint32_t)popc64(m);
+      __syncthreads();
+      uint32_t before = 0, total = 0;
+      for (int t = 0; t < nt / 64; t++) {
+        before += t < wv ? wcount[t] : 0;
+        total += wcount[t];
+      }
+      const uint32_t last = c0 + nt - 1 < M ? buf[c0 + nt - 1] : FG_NONE;
+      __syncthreads();
+      if (keep) buf[u + before + popc64(m & lanes_below())] = x;
+      if (tid == 0) carry = last;
+      u += total;
+      __syncthreads();
+    }
+    uint32_t* dst = tmp + o0 + a0;
+    for (int64_t j = tid; j < o; j += nt) {
+      const uint32_t x = ids[o0 + j];
+      int64_t lo = 0, hi = u;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (buf[mid] < x) lo = mid + 1;
+        else hi = mid;
+      }
+      dst[j + lo] = x;
+    }
+    for (int64_t i = tid; i < u; i += nt) {
+      const uint32_t x = buf[i];
+      int64_t lo = 0, hi = o;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (ids[o0 + mid] < x) lo = mid + 1;
+        else hi = mid;
+      }
+      dst[i + lo] = x;
+    }
+    if (tid == 0) newlen[v] = (uint32_t)(o + u);
+    __syncthreads();
+  }
+}
+
 // Copy row v from its upper-bound slot to its final offset.
 __global__ void __launch_bounds__(64) k_compact_rows(int64_t n, const uint64_t* off, const uint64_t* addoff,
                                                      const uint32_t* tmp, const uint64_t* noff,
@@ -410,6 +512,44 @@ hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t st) {
   return hipGetLastError();
 }
 
+__global__ void k_scatter_parents(const uint32_t* local, int64_t ni, uint32_t T, int64_t N, int64_t o,
+                                  uint32_t* global) {
+  const int64_t total = (int64_t)T * ni;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = i / ni, j = i - t * ni;
+    const uint32_t v = local[i];
+    global[t * N + o + j] = v == FG_NONE ? FG_NONE : (uint32_t)(v + o);
+  }
+}
+
+hipError_t scatter_parents(const uint32_t* local, int64_t ni, uint32_t T, int64_t N, int64_t o, uint32_t* global,
+                           hipStream_t st) {
+  k_scatter_parents<<<blocks_for((int64_t)T * ni, 256), 256, 0, st>>>(local, ni, T, N, o, global);
+  return hipGetLastError();
+}
+
+__global__ void k_localize_graph(const uint32_t* nbrs, const uint32_t* cnt, const uint32_t* parent0, int64_t ni,
+                                 int R, int64_t o, uint32_t* out_nbrs, uint32_t* out_cnt, uint32_t* out_parent) {
+  const int64_t total = ni * R;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = i / R;
+    const uint32_t v = nbrs[o * R + i];
+    out_nbrs[i] = v == FG_NONE ? FG_NONE : (uint32_t)(v - o);
+    if (i - j * R == 0) {
+      out_cnt[j] = cnt[o + j];
+      const uint32_t p = parent0[o + j];
+      out_parent[j] = p == FG_NONE ? FG_NONE : (uint32_t)(p - o);
+    }
+  }
+}
+
+hipError_t localize_graph(const uint32_t* nbrs, const uint32_t* cnt, const uint32_t* parent0, int64_t ni, int R,
+                          int64_t o, uint32_t* out_nbrs, uint32_t* out_cnt, uint32_t* out_parent, hipStream_t st) {
+  k_localize_graph<<<blocks_for(ni * R, 256), 256, 0, st>>>(nbrs, cnt, parent0, ni, R, o, out_nbrs, out_cnt,
+                                                             out_parent);
+  return hipGetLastError();
+}
+
 hipError_t fill_u64(uint64_t* p, uint64_t v, int64_t count, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   k_fill_u64<<<blocks_for(count, 1024), 256, 0, st>>>(p, v, count);
@@ -445,6 +585,13 @@ hipError_t edges_scatter(int64_t n, const uint32_t* rows, const uint32_t* cnt, i
   if (nitems <= 0) return hipSuccess;
   k_edges_scatter<<<blocks_for(nitems * R, 1024), 256, 0, st>>>(n, rows, cnt, R, b, B, nitems, own, rev,
                                                                 off, cursor, out);
+  return hipGetLastError();
+}
+
+hipError_t merge_big_rows_dev(const uint32_t* big, const uint32_t* nbig, const uint64_t* off, const uint32_t* ids,
+                              const uint64_t* addoff, const uint32_t* addbuf, uint32_t* scratch, uint32_t* tmp,
+                              uint32_t* newlen, hipStream_t st) {
+  k_merge_big_dev<<<64, 1024, 0, st>>>(big, nbig, off, ids, addoff, addbuf, scratch, tmp, newlen);
   return hipGetLastError();
 }
 

@@ -49,6 +49,13 @@ hipError_t make_screen(const Shape& s, int screen, uint8_t* xs, float* err, floa
 
 // Small utilities (fg_graph.hip).
 hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t st);
+// Batched builds (fg_graph.hip): parents of one instance's T trees (T x ni,
+// local ids) into the shared id space (T x N, offset o); rows of the shared
+// graph back to one instance's ids.
+hipError_t scatter_parents(const uint32_t* local, int64_t ni, uint32_t T, int64_t N, int64_t o, uint32_t* global,
+                           hipStream_t st);
+hipError_t localize_graph(const uint32_t* nbrs, const uint32_t* cnt, const uint32_t* parent0, int64_t ni, int R,
+                          int64_t o, uint32_t* out_nbrs, uint32_t* out_cnt, uint32_t* out_parent, hipStream_t st);
 hipError_t fill_u64(uint64_t* p, uint64_t v, int64_t count, hipStream_t st);
 // Exclusive scan of `count` uint32 values into uint64 offsets (count+1 entries).
 size_t scan_scratch_bytes(int64_t count);
@@ -62,7 +69,9 @@ hipError_t edges_scatter(int64_t n, const uint32_t* rows, const uint32_t* cnt, i
                          int64_t nitems, bool own, bool rev, const uint64_t* off, uint32_t* cursor,
                          uint32_t* out, hipStream_t st);
 // Rows whose additions exceed the on-chip bound are listed in big[] (count
-// in *nbig) and finished by merge_big_rows().
+// in *nbig) and finished by merge_big_rows() (host-planned segmented sort)
+// or by merge_big_rows_dev() (device only, for captured streams; scratch
+// holds 2 * additions entries).
 hipError_t merge_rows(int64_t n, const uint64_t* off, const uint32_t* ids, const uint64_t* addoff,
                       const uint32_t* addbuf, uint32_t* tmp, uint32_t* newlen, uint32_t* big, uint32_t* nbig,
                       hipStream_t st);
@@ -77,6 +86,9 @@ constexpr int kSegTilePositions = 256;
 // Sort each segment of keys (keys2: same-size scratch).  hsegs mirrors dsegs.
 hipError_t segsort_u64(uint64_t* keys, uint64_t* keys2, const KSeg* dsegs, const std::vector<KSeg>& hsegs,
                        KTile* dtiles, size_t tile_cap, hipStream_t st);
+hipError_t merge_big_rows_dev(const uint32_t* big, const uint32_t* nbig, const uint64_t* off, const uint32_t* ids,
+                              const uint64_t* addoff, const uint32_t* addbuf, uint32_t* scratch, uint32_t* tmp,
+                              uint32_t* newlen, hipStream_t st);
 hipError_t merge_big_rows(const uint32_t* big, uint32_t nbig, const uint64_t* off, const uint32_t* ids,
                           const uint64_t* addoff, const uint32_t* addbuf, uint32_t* tmp, uint32_t* newlen,
                           KSeg* dsegs, KTile* dtiles, size_t tile_cap, uint64_t* keys, uint64_t* keys2,

@@ -90,6 +90,8 @@ _SIGS = {
     "fg_search": (C.c_int, [P, P, P, C.c_int64, C.c_uint32, C.c_uint32, P, P, P, P,
                             C.c_size_t, P]),
     "fg_graph_hash": (C.c_int, [P, P, P]),
+    "fg_batched_workspace_size": (C.c_size_t, [P, P, C.c_uint32]),
+    "fg_build_graph_batched": (C.c_int, [P, P, P, C.c_uint32, P, P, C.c_size_t, P, C.c_int, P]),
     "fg_screen_row_bytes": (C.c_int64, [C.c_int32, C.c_uint32]),
     "fg_screen_copy": (C.c_int, [P, C.c_uint32, P, P, P, P, P]),
     "fg_leaf_knn_workspace_size": (C.c_size_t, [P]),
@@ -254,6 +256,32 @@ def search(data: fg_data, graph: fg_graph, queries: torch.Tensor, k: int, L: int
     _check(lib().fg_search(C.byref(data), C.byref(graph), _ptr(queries), queries.shape[0], k,
                            L, _ptr(out_ids), _ptr(out_d), _ptr(out_evals), wp, wn,
                            _stream(stream)))
+
+
+def _ptr_array(structs):
+    arr = (C.c_void_p * len(structs))(*[C.addressof(x) for x in structs])
+    return arr
+
+
+def batched_workspace_size(datas, paramses) -> int:
+    return int(lib().fg_batched_workspace_size(_ptr_array(datas), _ptr_array(paramses), len(datas)))
+
+
+def build_graph_batched(datas, paramses, seeds, graphs, ws=None, use_hipgraph=False, stream=None):
+    """Build len(datas) independent graphs together (fg_build_graph_batched);
+    returns the summed counters and the workspace (reusable)."""
+    count = len(datas)
+    if ws is None:
+        nb = batched_workspace_size(datas, paramses)
+        if nb == 0:
+            _check(FG_EINVAL)
+        ws = torch.empty(nb + 256, dtype=torch.uint8, device=datas[0]._keep[0].device)
+    wp, wn = _ws(ws)
+    sd = (C.c_uint64 * count)(*seeds)
+    c = fg_counters()
+    _check(lib().fg_build_graph_batched(_ptr_array(datas), _ptr_array(paramses), sd, count, _ptr_array(graphs),
+                                        wp, wn, _stream(stream), 1 if use_hipgraph else 0, C.byref(c)))
+    return c.as_dict(), ws
 
 
 def graph_hash(graph: fg_graph, stream=None) -> int:
