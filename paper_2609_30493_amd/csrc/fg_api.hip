@@ -850,8 +850,9 @@ fg_status fg_build_graph(const fg_data* data, uint64_t seed, const fg_params* pa
 // [off_i, off_i + n_i) with off_i a multiple of B, so a point's block is the
 // same as in its own build; rows are copied into one matrix whose stride fits
 // the widest instance, zero-padded (zero chunks add exactly nothing in the
-// declared order, so every distance is that of the instance alone).  The
-// scaffold is built per instance; each block is one harvest launch over all
+// declared order, so every distance is that of the instance alone).  One
+// tree-builder pass grows every instance's trees; each block is one harvest
+// launch over all
 // instances (per-point instance, roots and beam width) and one merge over the
 // whole id space; finalize runs once; each instance's graph is copied back
 // in its own ids.
@@ -864,14 +865,13 @@ struct BatchPlan {
   int ef_max = 0;
   std::vector<int64_t> off;
   WsMap m;
-  size_t x_at = 0, inst_at = 0, roots_at = 0, ef_at = 0, nbrs_at = 0, gcnt_at = 0, tpl_at = 0;
+  size_t x_at = 0, inst_at = 0, roots_at = 0, ef_at = 0, nbrs_at = 0, gcnt_at = 0;
   size_t total = 0;
 };
 
 bool plan_batch(const fg_data* const* data, const fg_params* const* params, uint32_t count, BatchPlan* bp) {
   if (!data || !params || count < 1 || count > 65535)
     return set_error("need 1 <= count <= 65535 instances and data/params arrays"), false;
-  int64_t nmax = 0;
   int dk = -1;
   for (uint32_t i = 0; i < count; i++) {
     Shape si;
@@ -889,7 +889,6 @@ bool plan_batch(const fg_data* const* data, const fg_params* const* params, uint
     const int64_t rb = (int64_t)si.Q * 16;
     bp->stride = rb > bp->stride ? rb : bp->stride;
     bp->ef_max = (int)b->ef_h > bp->ef_max ? (int)b->ef_h : bp->ef_max;
-    nmax = si.n > nmax ? si.n : nmax;
   }
   const int64_t Be = b_eff(params[0]);
   bp->off.assign(count + 1, 0);
@@ -918,7 +917,6 @@ bool plan_batch(const fg_data* const* data, const fg_params* const* params, uint
   bp->ef_at = take((uint64_t)count * 4);
   bp->nbrs_at = take(N * R * 4);
   bp->gcnt_at = take(N * 4);
-  bp->tpl_at = take(T * (uint64_t)nmax * 4);
   bp->total = o;
   return true;
 }
@@ -958,9 +956,7 @@ fg_status fg_build_graph_batched(const fg_data* const* data, const fg_params* co
   int* inst_ef = reinterpret_cast<int*>(at(ws_dev, bp.ef_at));
   uint32_t* gnbrs = reinterpret_cast<uint32_t*>(at(ws_dev, bp.nbrs_at));
   uint32_t* gcnt = reinterpret_cast<uint32_t*>(at(ws_dev, bp.gcnt_at));
-  uint32_t* tpl = reinterpret_cast<uint32_t*>(at(ws_dev, bp.tpl_at));
   uint32_t* tparent = reinterpret_cast<uint32_t*>(at(ws_dev, m.tparent));
-  uint32_t* rdev = reinterpret_cast<uint32_t*>(at(ws_dev, m.roots));
   uint64_t* off[2] = {reinterpret_cast<uint64_t*>(at(ws_dev, m.off[0])),
                       reinterpret_cast<uint64_t*>(at(ws_dev, m.off[1]))};
   uint32_t* ids[2] = {reinterpret_cast<uint32_t*>(at(ws_dev, m.ids[0])),
@@ -992,22 +988,14 @@ fg_status fg_build_graph_batched(const fg_data* const* data, const fg_params* co
   if (r) return r;
   FG_HIP(hipStreamSynchronize(st));  // the host tables above must outlive their copies
 
-  // Scaffold: T trees per instance, parents moved into the shared id space.
-  FG_HIP(fill_u32(tparent, FG_NONE, (int64_t)T * N, st));
+  // Scaffold: every instance's T trees in one builder pass, in the shared ids.
   unsigned long long sat_evals = 0;
-  for (uint32_t i = 0; i < count; i++) {
-    Shape si = bp.s;
-    si.x = X + bp.off[i] * bp.stride;
-    si.n = data[i]->n;
-    SatWs sw;
-    sat_workspace_bytes(si.n, T, &sw);
-    FG_HIP(hipMemcpyAsync(rdev, &hroots_local[(size_t)i * T], T * 4, hipMemcpyHostToDevice, st));
-    unsigned long long ev = 0;
+  {
+    std::vector<SatInstance> si(count);
+    for (uint32_t i = 0; i < count; i++) si[i] = SatInstance{bp.off[i], data[i]->n, &hroots_local[(size_t)i * T]};
     int status = 0;
-    FG_HIP(sat_build(si, rdev, T, tpl, at(ws_dev, m.sat), sw, st, &ev, &status));
+    FG_HIP(sat_build_multi(bp.s, T, si, tparent, at(ws_dev, m.sat), m.satw, st, &sat_evals, &status));
     if (status) return status_error(status);
-    sat_evals += ev;
-    FG_HIP(scatter_parents(tpl, si.n, T, N, bp.off[i], tparent, st));
   }
   r = scaffold_csr_launch(N, T, tparent, off[0], ids[0], ws_dev, m, st);
   if (r) return r;

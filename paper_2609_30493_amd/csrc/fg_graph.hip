@@ -512,22 +512,6 @@ hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t st) {
   return hipGetLastError();
 }
 
-__global__ void k_scatter_parents(const uint32_t* local, int64_t ni, uint32_t T, int64_t N, int64_t o,
-                                  uint32_t* global) {
-  const int64_t total = (int64_t)T * ni;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t t = i / ni, j = i - t * ni;
-    const uint32_t v = local[i];
-    global[t * N + o + j] = v == FG_NONE ? FG_NONE : (uint32_t)(v + o);
-  }
-}
-
-hipError_t scatter_parents(const uint32_t* local, int64_t ni, uint32_t T, int64_t N, int64_t o, uint32_t* global,
-                           hipStream_t st) {
-  k_scatter_parents<<<blocks_for((int64_t)T * ni, 256), 256, 0, st>>>(local, ni, T, N, o, global);
-  return hipGetLastError();
-}
-
 __global__ void k_localize_graph(const uint32_t* nbrs, const uint32_t* cnt, const uint32_t* parent0, int64_t ni,
                                  int R, int64_t o, uint32_t* out_nbrs, uint32_t* out_cnt, uint32_t* out_parent) {
   const int64_t total = ni * R;

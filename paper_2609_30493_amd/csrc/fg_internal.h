@@ -49,11 +49,8 @@ hipError_t make_screen(const Shape& s, int screen, uint8_t* xs, float* err, floa
 
 // Small utilities (fg_graph.hip).
 hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t st);
-// Batched builds (fg_graph.hip): parents of one instance's T trees (T x ni,
-// local ids) into the shared id space (T x N, offset o); rows of the shared
-// graph back to one instance's ids.
-hipError_t scatter_parents(const uint32_t* local, int64_t ni, uint32_t T, int64_t N, int64_t o, uint32_t* global,
-                           hipStream_t st);
+// Batched builds (fg_graph.hip): rows of the shared graph back to one
+// instance's ids.
 hipError_t localize_graph(const uint32_t* nbrs, const uint32_t* cnt, const uint32_t* parent0, int64_t ni, int R,
                           int64_t o, uint32_t* out_nbrs, uint32_t* out_cnt, uint32_t* out_parent, hipStream_t st);
 hipError_t fill_u64(uint64_t* p, uint64_t v, int64_t count, hipStream_t st);

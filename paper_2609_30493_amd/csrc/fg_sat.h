@@ -1,5 +1,6 @@
 // fg_sat.h -- state of the spatial-approximation-tree forest builder.
 #pragma once
+#include <vector>
 #include "fg_internal.h"
 
 namespace fg {
@@ -61,6 +62,17 @@ size_t sat_workspace_bytes(int64_t n, uint32_t T, SatWs* w);
 // Build T trees rooted at roots (device); parent is T x n (device).
 hipError_t sat_build(const Shape& s, const uint32_t* roots, uint32_t T, uint32_t* parent, char* ws,
                      const SatWs& w, hipStream_t st, unsigned long long* evals, int* status);
+// The trees of several instances at once: instance i owns the ids
+// [off, off + n) of s (rows of other instances are never compared with
+// them) and its trees are rooted at off + roots[t] (roots: host, local ids,
+// T <= 64).  parent is T x s.n in the shared ids; ids of no instance keep
+// 0xFFFFFFFF.  Every instance gets exactly the trees of its own build.
+struct SatInstance {
+  int64_t off, n;
+  const uint32_t* roots;
+};
+hipError_t sat_build_multi(const Shape& s, uint32_t T, const std::vector<SatInstance>& inst, uint32_t* parent,
+                           char* ws, const SatWs& w, hipStream_t st, unsigned long long* evals, int* status);
 // Directed edges of the T trees in both directions, grouped by source row
 // (unsorted, with repeats) into tmp_ids at offsets off_tmp.
 hipError_t tree_edges_csr(int64_t n, uint32_t T, const uint32_t* parent, uint32_t* deg,

@@ -616,7 +616,8 @@ int blocks_for(int64_t count, int per_block) {
 
 }  // namespace
 
-hipError_t sat_iota(uint32_t* perm, int64_t n, uint32_t T, const uint32_t* roots, hipStream_t st);
+hipError_t sat_iota(uint32_t* perm, int64_t n, uint32_t T, int64_t off, int64_t ni, const uint32_t* roots,
+                    hipStream_t st);
 hipError_t sat_clear_counts(SatArgs& a, unsigned nt, hipStream_t st);
 
 size_t sat_workspace_bytes(int64_t n, uint32_t T, SatWs* w) {
@@ -656,8 +657,20 @@ size_t sat_workspace_bytes(int64_t n, uint32_t T, SatWs* w) {
 // array; counters[0..2] (device) accumulate distance evaluations.
 hipError_t sat_build(const Shape& s, const uint32_t* roots, uint32_t T, uint32_t* parent, char* ws,
                      const SatWs& w, hipStream_t st, unsigned long long* host_evals, int* host_status) {
+  std::vector<uint32_t> hroots(T);
+  hipError_t e = hipMemcpyAsync(hroots.data(), roots, T * 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  std::vector<SatInstance> one{SatInstance{0, s.n, hroots.data()}};
+  return sat_build_multi(s, T, one, parent, ws, w, st, host_evals, host_status);
+}
+
+hipError_t sat_build_multi(const Shape& s, uint32_t T, const std::vector<SatInstance>& inst, uint32_t* parent,
+                           char* ws, const SatWs& w, hipStream_t st, unsigned long long* host_evals,
+                           int* host_status) {
   KSet K;
   if (!pick_kset(s.dk, s.Q, &K)) return hipErrorInvalidValue;
+  if (T > 64) return hipErrorInvalidValue;
   const int64_t n = s.n;
   SatArgs a{};
   a.X = RowSet{s.x, s.stride, s.Q};
@@ -698,20 +711,22 @@ hipError_t sat_build(const Shape& s, const uint32_t* roots, uint32_t T, uint32_t
   CK(fill_u32(reinterpret_cast<uint32_t*>(ctl), 0, sizeof(SatCtl) / 4, st));
   CK(fill_u32(parent, FG_NONE, (int64_t)tn, st));
   CK(fill_u32(a.ccount, 0, (int64_t)tn, st));
-  // Tree t's first bag: positions [t*n, t*n + n - 1) hold every id but root_t.
-  CK(sat_iota(a.perm, n, T, roots, st));
-  std::vector<uint32_t> hroots(T);
-  CK(hipMemcpyAsync(hroots.data(), roots, T * 4, hipMemcpyDeviceToHost, st));
-  CK(hipStreamSynchronize(st));
+  // Tree t of instance i: its first bag at positions [t*n + off, t*n + off +
+  // n_i - 1) holds every id of the instance but its root.
   std::vector<SatSeg> large, init_small;
-  for (uint32_t t = 0; t < T && n > 1; t++) {
-    SatSeg sg{};
-    sg.t = t;
-    sg.center = hroots[t];
-    sg.start = (uint64_t)t * n;
-    sg.len = (uint32_t)(n - 1);
-    (sg.len > (uint32_t)kSmall ? large : init_small).push_back(sg);
+  for (const SatInstance& in : inst) {
+    if (in.n <= 1) continue;
+    CK(sat_iota(a.perm, n, T, in.off, in.n, in.roots, st));
+    for (uint32_t t = 0; t < T; t++) {
+      SatSeg sg{};
+      sg.t = t;
+      sg.center = (uint32_t)(in.off + in.roots[t]);
+      sg.start = (uint64_t)t * n + (uint64_t)in.off;
+      sg.len = (uint32_t)(in.n - 1);
+      (sg.len > (uint32_t)kSmall ? large : init_small).push_back(sg);
+    }
   }
+  if (init_small.size() > w.cap_small) return hipErrorOutOfMemory;
   uint32_t n_small_host = (uint32_t)init_small.size();
   if (n_small_host) {
     CK(hipMemcpyAsync(a.small, init_small.data(), init_small.size() * sizeof(SatSeg),
@@ -803,13 +818,18 @@ hipError_t sat_build(const Shape& s, const uint32_t* roots, uint32_t T, uint32_t
 }
 
 namespace {
-__global__ void k_sat_iota(uint32_t* perm, int64_t n, uint32_t T, const uint32_t* roots) {
-  int64_t total = (int64_t)T * (n - 1);
+struct RootList {
+  uint32_t r[64];
+};
+// Tree t's first bag of one instance (ids [off, off + ni)): every id but
+// off + root_t, in id order.
+__global__ void k_sat_iota(uint32_t* perm, int64_t n, uint32_t T, int64_t off, int64_t ni, RootList roots) {
+  int64_t total = (int64_t)T * (ni - 1);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
-    int64_t t = i / (n - 1), j = i - t * (n - 1);
-    uint32_t r = roots[t];
-    perm[t * n + j] = (uint32_t)(j < (int64_t)r ? j : j + 1);
+    int64_t t = i / (ni - 1), j = i - t * (ni - 1);
+    uint32_t r = roots.r[t];
+    perm[t * n + off + j] = (uint32_t)(off + (j < (int64_t)r ? j : j + 1));
   }
 }
 __global__ void __launch_bounds__(64) k_sat_clear_counts(SatArgs A) {
@@ -820,9 +840,12 @@ __global__ void __launch_bounds__(64) k_sat_clear_counts(SatArgs A) {
 }
 }  // namespace
 
-hipError_t sat_iota(uint32_t* perm, int64_t n, uint32_t T, const uint32_t* roots, hipStream_t st) {
-  if (n <= 1) return hipSuccess;
-  k_sat_iota<<<blocks_for((int64_t)T * (n - 1), 256), 256, 0, st>>>(perm, n, T, roots);
+hipError_t sat_iota(uint32_t* perm, int64_t n, uint32_t T, int64_t off, int64_t ni, const uint32_t* roots,
+                    hipStream_t st) {
+  if (ni <= 1) return hipSuccess;
+  RootList rl{};
+  for (uint32_t t = 0; t < T && t < 64; t++) rl.r[t] = roots[t];
+  k_sat_iota<<<blocks_for((int64_t)T * (ni - 1), 256), 256, 0, st>>>(perm, n, T, off, ni, rl);
   return hipGetLastError();
 }
 
