@@ -90,7 +90,9 @@ typedef struct {
  * of each harvest search's on-chip visited table, 2048 or 4096 (0 = 2048
  * when ef_h <= 128, else 4096; ef_h > 128 always uses 4096).  A search
  * whose expanded set exceeds half the table size fails with FG_ECAPACITY.
- * screen is an fg_screen; it never changes the graph either. */
+ * screen is an fg_screen; it never changes the graph either.  waves_per_cu
+ * caps the resident harvest searches per compute unit (0 = as many as fit);
+ * another knob that never changes the graph (see fg_autotune). */
 typedef struct {
   uint32_t T;
   uint32_t ef_h;
@@ -100,6 +102,8 @@ typedef struct {
   uint32_t reprune_all;
   uint32_t beam_table_slots;
   uint32_t screen;
+  uint32_t waves_per_cu;
+  uint32_t reserved;
 } fg_params;
 
 /* Compressed rows in device memory: row v is ids_dev[off_dev[v] ..
@@ -275,6 +279,19 @@ int64_t fg_screen_row_bytes(int32_t d, uint32_t screen);
 fg_status fg_screen_copy(const fg_data* data, uint32_t screen, void* xs_dev,
                          float* err_dev, float* norm_dev, float* sinv_dev,
                          void* stream);
+
+/* Autotuning of the harvest's knobs (none changes the graph): the
+ * visited-table size (beam_table_slots 2048 / 4096, where ef_h allows) and
+ * the resident searches per compute unit (waves_per_cu).  On the first
+ * min(n, 50000) rows it builds a scaffold, then times block 0's harvest
+ * for each candidate (best of two) and writes the fastest into *tuned (a
+ * copy of *params with those two fields set).  With cache_path != NULL the
+ * result is looked up in / appended to that text file, one line per
+ * (dtype, metric, row chunks, ef_h, R, T, B, log2 n).  The workspace is the
+ * one fg_workspace_size gives for data and params.  Synchronises `stream`. */
+fg_status fg_autotune(const fg_data* data, const fg_params* params,
+                      const char* cache_path, void* ws_dev, size_t ws_bytes,
+                      void* stream, fg_params* tuned);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* fg_last_error(void);

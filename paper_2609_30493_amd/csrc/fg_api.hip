@@ -6,6 +6,9 @@
 #include <string>
 #include <vector>
 
+#include <cstdio>
+#include <cstring>
+
 #include "fg_internal.h"
 #include "fg_sat.h"
 
@@ -60,6 +63,7 @@ bool check_params(const fg_params* p, int64_t n, bool need_ef = true) {
   if (p->beam_table_slots != 0 && p->beam_table_slots != 2048 && p->beam_table_slots != 4096)
     return set_error("beam_table_slots must be 0, 2048 or 4096"), false;
   if (p->screen > FG_SCREEN_FP8E4M3) return set_error("screen must be an fg_screen"), false;
+  if (p->waves_per_cu > 64) return set_error("waves_per_cu must be 0..64"), false;
   return true;
 }
 
@@ -209,7 +213,7 @@ fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* id
   const int ef = bi ? bi->ef_max : (int)P->ef_h;
   const int hslots = beam_table_slots(ef, false, table_request(P));
   const int screen = (int)P->screen;
-  int grid = beam_grid(s, ef, false, hslots, screen);
+  int grid = beam_grid(s, ef, false, hslots, screen, (int)P->waves_per_cu);
   if (grid <= 0) return set_error("no beam kernel for this row size / ef_h"), FG_EUNSUPPORTED;
   BeamArgs a{};
   a.x = s.x;
@@ -845,6 +849,127 @@ fg_status fg_build_graph(const fg_data* data, uint64_t seed, const fg_params* pa
   return status_error(c.status);
 }
 
+// ---------------------------------------------------------------- autotune
+fg_status fg_autotune(const fg_data* data, const fg_params* params, const char* cache_path, void* ws_dev,
+                      size_t ws_bytes, void* stream, fg_params* tuned) {
+  Shape s;
+  if (!make_shape(data, &s)) return FG_EINVAL;
+  if (!check_params(params, s.n)) return FG_EINVAL;
+  if (!check_screen(params, s)) return FG_EUNSUPPORTED;
+  if (!tuned) return set_error("tuned is NULL"), FG_EINVAL;
+  int lg = 0;
+  while ((1ll << (lg + 1)) <= s.n) lg++;
+  char key[160];
+  snprintf(key, sizeof(key), "dk=%d Q=%d ef=%u R=%u T=%u B=%u screen=%u lgn=%d", s.dk, s.Q, params->ef_h,
+           params->R, params->T, b_eff(params), params->screen, lg);
+  *tuned = *params;
+  if (cache_path) {
+    if (FILE* f = fopen(cache_path, "r")) {
+      char line[256];
+      bool hit = false;
+      while (fgets(line, sizeof(line), f)) {
+        unsigned tb = 0, wv = 0;
+        const char* bar = strchr(line, '|');
+        if (!bar || (size_t)(bar - line) != strlen(key) || strncmp(line, key, strlen(key))) continue;
+        if (sscanf(bar + 1, " table=%u waves=%u", &tb, &wv) == 2 && (tb == 2048 || tb == 4096) && wv <= 64) {
+          tuned->beam_table_slots = tb;
+          tuned->waves_per_cu = wv;
+          hit = true;
+        }
+      }
+      fclose(f);
+      if (hit) return FG_OK;
+    }
+  }
+  // A prefix sample with its own scaffold; block 0 of its harvest is timed.
+  Shape ss = s;
+  ss.n = s.n < 50000 ? s.n : 50000;
+  fg_params P = *params;
+  const uint32_t T = P.T;
+  if ((int64_t)T > ss.n) return set_error("fewer sample points than trees"), FG_EINVAL;
+  WsMap m = ws_map(ss.n, &P, ss.d);
+  if (!check_ws(ws_dev, ws_bytes, m)) return FG_ENOMEM;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<uint32_t> hroots(T);
+  fg_status r = fg_roots(1, ss.n, T, hroots.data());
+  if (r) return r;
+  uint32_t* roots = reinterpret_cast<uint32_t*>(at(ws_dev, m.roots));
+  uint32_t* tparent = reinterpret_cast<uint32_t*>(at(ws_dev, m.tparent));
+  uint64_t* off0 = reinterpret_cast<uint64_t*>(at(ws_dev, m.off[0]));
+  uint32_t* ids0 = reinterpret_cast<uint32_t*>(at(ws_dev, m.ids[0]));
+  uint32_t* rows = reinterpret_cast<uint32_t*>(at(ws_dev, m.rows));
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(at(ws_dev, m.cnt));
+  r = reset_ctl(ws_dev, m, st);
+  if (r) return r;
+  FG_HIP(hipMemcpyAsync(roots, hroots.data(), T * 4, hipMemcpyHostToDevice, st));
+  unsigned long long ev = 0;
+  int status = 0;
+  FG_HIP(sat_build(ss, roots, T, tparent, at(ws_dev, m.sat), m.satw, st, &ev, &status));
+  if (status) return status_error(status);
+  r = scaffold_csr_launch(ss.n, T, tparent, off0, ids0, ws_dev, m, st);
+  if (r) return r;
+  r = screen_launch(ss, &P, ws_dev, m, st);
+  if (r) return r;
+  FG_HIP(fill_u32(reinterpret_cast<uint32_t*>(at(ws_dev, m.bits)), 0, (int64_t)kMaxWaveSlots * m.spill_words, st));
+  std::vector<unsigned> tables;
+  if (P.ef_h <= 128) tables = {2048, 4096};
+  else tables = {4096};
+  hipEvent_t e0, e1;
+  FG_HIP(hipEventCreate(&e0));
+  FG_HIP(hipEventCreate(&e1));
+  float best = 3.0e38f;
+  unsigned best_tb = tables[0], best_wv = 0;
+  for (unsigned tb : tables) {
+    P.beam_table_slots = tb;
+    P.waves_per_cu = 0;
+    const int hs = beam_table_slots((int)P.ef_h, false, table_request(&P));
+    int full = beam_grid(ss, (int)P.ef_h, false, hs, (int)P.screen) / num_cus_host();
+    if (full < 1) full = 1;
+    for (unsigned wv : {0u, (unsigned)(full * 3 / 4), (unsigned)(full / 2)}) {
+      if (wv == 0 ? false : (wv < 1 || (int)wv >= full)) continue;
+      P.waves_per_cu = wv;
+      float t_best = 3.0e38f;
+      for (int rep = 0; rep < 2; rep++) {
+        fg_status rr = FG_OK;
+        if (hipEventRecord(e0, st) != hipSuccess) rr = FG_EHIP;
+        if (!rr) rr = harvest_launch(ss, off0, ids0, roots, &P, 0, rows, cnt, ws_dev, m, st);
+        if (!rr && hipEventRecord(e1, st) != hipSuccess) rr = FG_EHIP;
+        if (!rr && hipEventSynchronize(e1) != hipSuccess) rr = FG_EHIP;
+        float ms = 0.f;
+        if (!rr && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rr = FG_EHIP;
+        if (rr) {
+          (void)hipEventDestroy(e0);
+          (void)hipEventDestroy(e1);
+          return rr;
+        }
+        t_best = ms < t_best ? ms : t_best;
+      }
+      if (t_best < best) {
+        best = t_best;
+        best_tb = tb;
+        best_wv = wv;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  Ctl c;
+  r = read_ctl(ws_dev, m, st, &c);
+  if (r) return r;
+  r = status_error(c.status);
+  if (r) return r;
+  tuned->beam_table_slots = best_tb;
+  tuned->waves_per_cu = best_wv;
+  if (cache_path) {
+    if (FILE* f = fopen(cache_path, "a")) {
+      fprintf(f, "%s| table=%u waves=%u  (block-0 harvest of %lld points: %.3f ms)\n", key, best_tb, best_wv,
+              (long long)ss.n, best);
+      fclose(f);
+    }
+  }
+  return FG_OK;
+}
+
 // ---------------------------------------------------------------- batched
 // Many independent instances in one id space: instance i owns ids
 // [off_i, off_i + n_i) with off_i a multiple of B, so a point's block is the
@@ -882,8 +1007,9 @@ bool plan_batch(const fg_data* const* data, const fg_params* const* params, uint
     const fg_params* a = params[0];
     const fg_params* b = params[i];
     if (b->T != a->T || b->R != a->R || b->alpha != a->alpha || b_eff(b) != b_eff(a) ||
-        b->reprune_all != a->reprune_all || b->beam_table_slots != a->beam_table_slots)
-      return set_error("batched instances must share T, R, alpha, B, reprune_all and beam_table_slots"), false;
+        b->reprune_all != a->reprune_all || b->beam_table_slots != a->beam_table_slots ||
+        b->waves_per_cu != a->waves_per_cu)
+      return set_error("batched instances must share T, R, alpha, B, reprune_all and the tuning knobs"), false;
     if (dk >= 0 && si.dk != dk) return set_error("batched instances must share dtype and metric"), false;
     dk = si.dk;
     const int64_t rb = (int64_t)si.Q * 16;

@@ -61,6 +61,8 @@ int num_cus() {
 
 }  // namespace
 
+int num_cus_host() { return num_cus(); }
+
 // Slots of the on-chip visited table actually used for this launch: the
 // search kernels and ef > 128 always use 4096; otherwise `hslots` (2048 or
 // 4096) as requested.
@@ -75,7 +77,7 @@ static void* pick_kernel(const Shape& s, int ef, bool search, int hslots, int sc
   return search ? pick<true>(s.dk, s.Q, ef, hslots) : pick<false>(s.dk, s.Q, ef, hslots);
 }
 
-int beam_grid(const Shape& s, int ef, bool search, int hslots, int screen) {
+int beam_grid(const Shape& s, int ef, bool search, int hslots, int screen, int waves_per_cu) {
   void* k = pick_kernel(s, ef, search, hslots, screen);
   if (!k) return 0;
   int per_cu = 0;
@@ -83,6 +85,7 @@ int beam_grid(const Shape& s, int ef, bool search, int hslots, int screen) {
           hipSuccess ||
       per_cu <= 0)
     per_cu = 4;
+  if (waves_per_cu > 0 && waves_per_cu < per_cu) per_cu = waves_per_cu;
   int g = per_cu * num_cus();
   return g < kMaxWaveSlots ? g : kMaxWaveSlots;
 }

@@ -35,9 +35,10 @@ bool make_shape(const fg_data* d, Shape* s);  // validates, sets error
 // screen (ScreenKind) selects the screened harvest kernels (fg_beam_sbf16.hip,
 // fg_beam_sfp8.hip: float32 rows of more than 16 chunks only).
 int beam_table_slots(int ef, bool search, int hslots);
-int beam_grid(const Shape& s, int ef, bool search, int hslots, int screen = SCR_NONE);
+int beam_grid(const Shape& s, int ef, bool search, int hslots, int screen = SCR_NONE, int waves_per_cu = 0);
 hipError_t launch_beam(const Shape& s, BeamArgs& a, bool search, int grid, int hslots, hipStream_t st,
                        int screen = SCR_NONE);
+int num_cus_host();  // compute units of the current device
 void* pick_screen_bf16(int dk, int Q, int ef, int hslots);
 void* pick_screen_fp8(int dk, int Q, int ef, int hslots);
 

@@ -35,7 +35,8 @@ class fg_data(C.Structure):
 class fg_params(C.Structure):
     _fields_ = [("T", C.c_uint32), ("ef_h", C.c_uint32), ("R", C.c_uint32),
                 ("alpha", C.c_float), ("B", C.c_uint32), ("reprune_all", C.c_uint32),
-                ("beam_table_slots", C.c_uint32), ("screen", C.c_uint32)]
+                ("beam_table_slots", C.c_uint32), ("screen", C.c_uint32),
+                ("waves_per_cu", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 SCREEN_NONE, SCREEN_BF16, SCREEN_FP8E4M3 = 0, 1, 2
@@ -90,6 +91,7 @@ _SIGS = {
     "fg_search": (C.c_int, [P, P, P, C.c_int64, C.c_uint32, C.c_uint32, P, P, P, P,
                             C.c_size_t, P]),
     "fg_graph_hash": (C.c_int, [P, P, P]),
+    "fg_autotune": (C.c_int, [P, P, C.c_char_p, P, C.c_size_t, P, P]),
     "fg_batched_workspace_size": (C.c_size_t, [P, P, C.c_uint32]),
     "fg_build_graph_batched": (C.c_int, [P, P, P, C.c_uint32, P, P, C.c_size_t, P, C.c_int, P]),
     "fg_screen_row_bytes": (C.c_int64, [C.c_int32, C.c_uint32]),
@@ -155,8 +157,9 @@ def make_data(x: torch.Tensor, metric: str = "l2") -> fg_data:
     return s
 
 
-def make_params(T, ef_h, R, alpha=1.2, B=1, reprune_all=0, beam_table_slots=0, screen=0) -> fg_params:
-    return fg_params(T, ef_h, R, alpha, B, reprune_all, beam_table_slots, screen)
+def make_params(T, ef_h, R, alpha=1.2, B=1, reprune_all=0, beam_table_slots=0, screen=0,
+                waves_per_cu=0) -> fg_params:
+    return fg_params(T, ef_h, R, alpha, B, reprune_all, beam_table_slots, screen, waves_per_cu, 0)
 
 
 def workspace_size(data: fg_data, params: fg_params) -> int:
@@ -256,6 +259,16 @@ def search(data: fg_data, graph: fg_graph, queries: torch.Tensor, k: int, L: int
     _check(lib().fg_search(C.byref(data), C.byref(graph), _ptr(queries), queries.shape[0], k,
                            L, _ptr(out_ids), _ptr(out_d), _ptr(out_evals), wp, wn,
                            _stream(stream)))
+
+
+def autotune(data: fg_data, params: fg_params, ws, cache_path=None, stream=None) -> fg_params:
+    """Tuned copy of params (visited-table size, searches per compute unit)."""
+    out = fg_params()
+    wp, wn = _ws(ws)
+    _check(lib().fg_autotune(C.byref(data), C.byref(params),
+                             None if cache_path is None else str(cache_path).encode(), wp, wn,
+                             _stream(stream), C.byref(out)))
+    return out
 
 
 def _ptr_array(structs):
