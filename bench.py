@@ -101,7 +101,7 @@ def cpu_baseline(w, n_sample: int, threads: int):
 
 
 def dsweep(args):
-    """Tab. 4 re-measured: adaptive cost per evaluation (the harvest of a
+    """Tab. 5 re-measured (Sec. 5.4): adaptive cost per evaluation (the harvest of a
     whole build, T=8 B=8 ef_h=128 R=64) against blocked cost per pair (every
     point's 64 nearest inside leaves of 2048 consecutive points on matrix
     cores, float32 and bfloat16 operands), n = 200,000 power-law rows

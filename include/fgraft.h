@@ -251,7 +251,7 @@ fg_status fg_search(const fg_data* data, const fg_graph* graph,
  * Copies the graph to the host; synchronises `stream`. */
 fg_status fg_graph_hash(const fg_graph* graph, void* stream, uint64_t* out);
 
-/* The blocked dense side of the random-access wall (Sec. 5.3, Tab. 4): for
+/* The blocked dense side of the random-access wall (Sec. 5.4, Tab. 5): for
  * every point, its R nearest other points (squared L2, ties by id) inside
  * its leaf of leaf_size consecutive ids ([l*leaf_size, (l+1)*leaf_size)),
  * all leaf_size^2 distances computed as |x|^2 + |y|^2 - 2<x,y> with the inner

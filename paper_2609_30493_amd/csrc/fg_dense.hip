@@ -245,33 +245,64 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
   }
 }
 
-__global__ void k_row_norms_f32(const float* X, int64_t n, int d, int64_t stride, float* out) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+// One wave per row, lanes over 4-element chunks (d % 4 == 0); the norm is
+// summed per lane, then across the wave.
+__device__ __forceinline__ float wave_sum_f32(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ void __launch_bounds__(256) k_row_norms_f32(const float* X, int64_t n, int d, int64_t stride, float* out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t i = w0; i < n; i += nw) {
     float s = 0.0f;
-    for (int k = 0; k < d; k++) s = __builtin_fmaf(X[i * stride + k], X[i * stride + k], s);
-    out[i] = s;
+    for (int c = lane; c < d / 4; c += 64) {
+      const float4 v = *reinterpret_cast<const float4*>(X + i * stride + 4 * c);
+      s = __builtin_fmaf(v.x, v.x, s);
+      s = __builtin_fmaf(v.y, v.y, s);
+      s = __builtin_fmaf(v.z, v.z, s);
+      s = __builtin_fmaf(v.w, v.w, s);
+    }
+    s = wave_sum_f32(s);
+    if (lane == 0) out[i] = s;
   }
 }
 
 // Rows rounded to bfloat16 (nearest even) into a copy whose row stride dp is
 // d rounded up to the staged chunk, zero-filled past d; norms of the rounded
 // rows.
-__global__ void k_to_bf16(const float* X, int64_t n, int d, int64_t stride, __bf16* Y, int dp, float* norms) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+__global__ void __launch_bounds__(256) k_to_bf16(const float* X, int64_t n, int d, int64_t stride, __bf16* Y, int dp,
+                                                 float* norms) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t i = w0; i < n; i += nw) {
     float s = 0.0f;
-    for (int k = 0; k < d; k++) {
-      __bf16 b = (__bf16)X[i * stride + k];
-      Y[i * dp + k] = b;
-      float f = (float)b;
-      s = __builtin_fmaf(f, f, s);
+    for (int c = lane; c < dp / 4; c += 64) {
+      float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (4 * c < d) v = *reinterpret_cast<const float4*>(X + i * stride + 4 * c);
+      const __bf16 b0 = (__bf16)v.x, b1 = (__bf16)v.y, b2 = (__bf16)v.z, b3 = (__bf16)v.w;
+      __bf16* y = Y + i * dp + 4 * c;
+      y[0] = b0;
+      y[1] = b1;
+      y[2] = b2;
+      y[3] = b3;
+      const float f0 = (float)b0, f1 = (float)b1, f2 = (float)b2, f3 = (float)b3;
+      s = __builtin_fmaf(f0, f0, s);
+      s = __builtin_fmaf(f1, f1, s);
+      s = __builtin_fmaf(f2, f2, s);
+      s = __builtin_fmaf(f3, f3, s);
     }
-    for (int k = d; k < dp; k++) Y[i * dp + k] = (__bf16)0.0f;
-    norms[i] = s;
+    s = wave_sum_f32(s);
+    if (lane == 0) norms[i] = s;
   }
 }
 
-int grid1(int64_t n) {
-  int64_t b = (n + 255) / 256;
+int grid1(int64_t n) {  // four rows (waves) per 256-thread block
+  int64_t b = (n + 3) / 4;
   return (int)(b < 65536 ? (b < 1 ? 1 : b) : 65536);
 }
 

@@ -8,7 +8,7 @@ its seed (numpy ``default_rng``), computes in float64 and casts once.
 The mixtures stand in for the paper's corpora (Sec. 2, "Systems"): an
 isotropic small-d mixture for the frozen-Graft case, a SIFT-128-shaped uint8
 mixture, a GloVe-100-shaped unit-norm anisotropic mixture, a GIST-960-shaped
-power-law mixture (Sec. 5.4, Tab. 4) and a batch of uneven instances.  None of
+power-law mixture (Sec. 5.4, Tab. 5) and a batch of uneven instances.  None of
 the public datasets is reproduced.
 """
 from __future__ import annotations
