@@ -362,8 +362,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=100_000)
-    ap.add_argument("--table", type=int, default=0, choices=(0, 2048, 4096),
-                    help="on-chip visited-table slots per search (0 = library default)")
+    ap.add_argument("--table", type=int, default=1024, choices=(0, 1024, 2048, 4096),
+                    help="on-chip visited-table slots per search (0 = library default); 1024 lets "
+                         "four searches share each SIMD on this workload")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed steps, copy 1 GiB device to device (a plain copy "
                          "kernel of known size, to scale profiler byte counters)")
@@ -433,7 +434,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": n, "d": w.d, "T": w.T, "B": w.B, "ef_h": w.ef_h,
                    "R": w.R, "alpha": w.alpha, "seed": w.build_seed,
-                   "beam_table_slots": args.table or (2048 if w.ef_h <= 128 else 4096)},
+                   "beam_table_slots": args.table or (2048 if w.ef_h <= 128 else 4096),
+                   "waves_per_cu": "max resident"},
         "build_s": wall / args.steps,
         "phase_ms": {k: t0_[k] for k in ("scaffold_ms", "harvest_ms", "merge_ms", "finalize_ms")},
         "harvest_evals_per_build": c0["harvest_evals"],

@@ -87,9 +87,11 @@ typedef struct {
  * (frozen Graft).  reprune_all = 0 re-prunes in finalize only the rows whose
  * symmetrised candidate set exceeds R; 1 re-prunes every row.
  * beam_table_slots is a tuning knob that never changes the graph: the size
- * of each harvest search's on-chip visited table, 2048 or 4096 (0 = 2048
- * when ef_h <= 128, else 4096; ef_h > 128 always uses 4096).  A search
- * whose expanded set exceeds half the table size fails with FG_ECAPACITY.
+ * of each harvest search's on-chip visited table, 1024, 2048 or 4096 (0 =
+ * 2048 when ef_h <= 128, else 4096; ef_h > 128 always uses 4096; 1024
+ * applies to ef_h <= 64 with rows of at most 256 bytes, else 2048 is used).
+ * Smaller tables let more searches run per compute unit.  A search whose
+ * expanded set exceeds half the table size fails with FG_ECAPACITY.
  * screen is an fg_screen; it never changes the graph either.  waves_per_cu
  * caps the resident harvest searches per compute unit (0 = as many as fit);
  * another knob that never changes the graph (see fg_autotune). */
@@ -281,7 +283,8 @@ fg_status fg_screen_copy(const fg_data* data, uint32_t screen, void* xs_dev,
                          void* stream);
 
 /* Autotuning of the harvest's knobs (none changes the graph): the
- * visited-table size (beam_table_slots 2048 / 4096, where ef_h allows) and
+ * visited-table size (beam_table_slots 1024 / 2048 / 4096, where ef_h and
+ * the row size allow) and
  * the resident searches per compute unit (waves_per_cu).  On the first
  * min(n, 50000) rows it builds a scaffold, then times block 0's harvest
  * for each candidate (best of two) and writes the fastest into *tuned (a

@@ -60,8 +60,9 @@ bool check_params(const fg_params* p, int64_t n, bool need_ef = true) {
     return set_error("need 1 <= ef_h <= 256"), false;
   if (p->R < 1 || p->R > 1024) return set_error("need 1 <= R <= 1024"), false;
   if (!isfinite(p->alpha) || p->alpha < 1.0f) return set_error("alpha must be finite and >= 1"), false;
-  if (p->beam_table_slots != 0 && p->beam_table_slots != 2048 && p->beam_table_slots != 4096)
-    return set_error("beam_table_slots must be 0, 2048 or 4096"), false;
+  if (p->beam_table_slots != 0 && p->beam_table_slots != 1024 && p->beam_table_slots != 2048 &&
+      p->beam_table_slots != 4096)
+    return set_error("beam_table_slots must be 0, 1024, 2048 or 4096"), false;
   if (p->screen > FG_SCREEN_FP8E4M3) return set_error("screen must be an fg_screen"), false;
   if (p->waves_per_cu > 64) return set_error("waves_per_cu must be 0..64"), false;
   return true;
@@ -81,7 +82,8 @@ uint32_t b_eff(const fg_params* p) { return p->B > 1 ? p->B : 1; }
 // when ef_h <= 128 (more searches resident per compute unit; measured faster
 // on the 1M uint8 build) and 4096 otherwise.
 int table_request(const fg_params* p) {
-  if (p->beam_table_slots == 2048 || p->beam_table_slots == 4096) return (int)p->beam_table_slots;
+  if (p->beam_table_slots == 1024 || p->beam_table_slots == 2048 || p->beam_table_slots == 4096)
+    return (int)p->beam_table_slots;
   return p->ef_h <= 128 ? 2048 : 4096;
 }
 
@@ -211,7 +213,7 @@ fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* id
   FG_HIP(fill_u64(reinterpret_cast<uint64_t*>(&ctl->queue), 0, 1, st));
   if (nitems == 0) return FG_OK;
   const int ef = bi ? bi->ef_max : (int)P->ef_h;
-  const int hslots = beam_table_slots(ef, false, table_request(P));
+  const int hslots = beam_table_slots(ef, false, table_request(P), beam_chunks_per_lane(s));
   const int screen = (int)P->screen;
   int grid = beam_grid(s, ef, false, hslots, screen, (int)P->waves_per_cu);
   if (grid <= 0) return set_error("no beam kernel for this row size / ef_h"), FG_EUNSUPPORTED;
@@ -871,7 +873,8 @@ fg_status fg_autotune(const fg_data* data, const fg_params* params, const char* 
         unsigned tb = 0, wv = 0;
         const char* bar = strchr(line, '|');
         if (!bar || (size_t)(bar - line) != strlen(key) || strncmp(line, key, strlen(key))) continue;
-        if (sscanf(bar + 1, " table=%u waves=%u", &tb, &wv) == 2 && (tb == 2048 || tb == 4096) && wv <= 64) {
+        if (sscanf(bar + 1, " table=%u waves=%u", &tb, &wv) == 2 && (tb == 1024 || tb == 2048 || tb == 4096) &&
+            wv <= 64) {
           tuned->beam_table_slots = tb;
           tuned->waves_per_cu = wv;
           hit = true;
@@ -912,7 +915,8 @@ fg_status fg_autotune(const fg_data* data, const fg_params* params, const char* 
   if (r) return r;
   FG_HIP(fill_u32(reinterpret_cast<uint32_t*>(at(ws_dev, m.bits)), 0, (int64_t)kMaxWaveSlots * m.spill_words, st));
   std::vector<unsigned> tables;
-  if (P.ef_h <= 128) tables = {2048, 4096};
+  if (P.ef_h <= 64 && beam_chunks_per_lane(ss) == 1) tables = {1024, 2048, 4096};
+  else if (P.ef_h <= 128) tables = {2048, 4096};
   else tables = {4096};
   hipEvent_t e0, e1;
   FG_HIP(hipEventCreate(&e0));
@@ -922,7 +926,7 @@ fg_status fg_autotune(const fg_data* data, const fg_params* params, const char* 
   for (unsigned tb : tables) {
     P.beam_table_slots = tb;
     P.waves_per_cu = 0;
-    const int hs = beam_table_slots((int)P.ef_h, false, table_request(&P));
+    const int hs = beam_table_slots((int)P.ef_h, false, table_request(&P), beam_chunks_per_lane(ss));
     int full = beam_grid(ss, (int)P.ef_h, false, hs, (int)P.screen) / num_cus_host();
     if (full < 1) full = 1;
     for (unsigned wv : {0u, (unsigned)(full * 3 / 4), (unsigned)(full / 2)}) {

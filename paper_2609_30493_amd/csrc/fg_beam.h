@@ -378,8 +378,18 @@ __device__ int prune_wave(const RowSet& X, float alpha, int R, const uint64_t* s
   return kept;
 }
 
+// Waves per SIMD the register budget aims at: more searches in flight hide
+// more gather latency.  Four for one-chunk rows with the 1024-slot table
+// (9 KB of LDS per wave), three for rows of one or two chunks per lane,
+// else whatever the registers allow.
+template <int NCH, int HS>
+constexpr int beam_waves_per_eu() {
+  return (NCH == 1 && HS == 1024) ? 4 : (NCH <= 2 ? 3 : 1);
+}
+
 template <int DK, int L, int NCH, int EFMAX, int HSLOTS, bool SEARCH, int SCR = SCR_NONE>
-__global__ void __launch_bounds__(64) k_beam(BeamArgs A) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(beam_waves_per_eu<NCH, HSLOTS>())))
+k_beam(BeamArgs A) {
   __shared__ WaveLDS<EFMAX, HSLOTS> S;
   const int lane = lane_id();
   const int g = lane % L;
@@ -389,7 +399,8 @@ __global__ void __launch_bounds__(64) k_beam(BeamArgs A) {
   uint64_t* E = A.Ebuf + wslot * (int64_t)A.Ecap;
   constexpr uint32_t HMASK = HSLOTS - 1;
   constexpr int HCAP = HSLOTS / 2 - 64;  // load <= 1/2; checked after every 64 insertions
-  constexpr int kRB = (NCH >= 16) ? 1 : 16 / NCH;
+  // rows in flight per lane group, sized to the register budget above
+  constexpr int kRB = (NCH >= 16) ? 1 : (NCH == 1 ? (HSLOTS == 1024 ? 8 : 12) : 16 / NCH);
   const RowSet X{A.x, A.stride, A.Q};
 
   unsigned long long my_evals = 0, my_exp = 0, my_pe = 0, my_spilled = 0, my_rej = 0;

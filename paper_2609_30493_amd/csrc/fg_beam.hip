@@ -11,6 +11,8 @@ namespace {
 
 template <int DK, int L, int NCH, int EFMAX, bool SEARCH>
 void* kernel_ptr(int hslots) {
+  if constexpr (!SEARCH && EFMAX <= 64 && NCH == 1)
+    if (hslots == 1024) return reinterpret_cast<void*>(&k_beam<DK, L, NCH, EFMAX, 1024, SEARCH>);
   if (hslots == 2048) return reinterpret_cast<void*>(&k_beam<DK, L, NCH, EFMAX, 2048, SEARCH>);
   return reinterpret_cast<void*>(&k_beam<DK, L, NCH, EFMAX, 4096, SEARCH>);
 }
@@ -63,11 +65,20 @@ int num_cus() {
 
 int num_cus_host() { return num_cus(); }
 
+int beam_chunks_per_lane(const Shape& s) {
+  if (s.Q <= 16) return 1;
+  if (s.Q <= 32) return 2;
+  if (s.Q <= 64) return 4;
+  return 16;
+}
+
 // Slots of the on-chip visited table actually used for this launch: the
-// search kernels and ef > 128 always use 4096; otherwise `hslots` (2048 or
-// 4096) as requested.
-int beam_table_slots(int ef, bool search, int hslots) {
+// search kernels and ef > 128 always use 4096; 1024 exists for ef <= 64 and
+// rows of one 16-byte chunk per lane (else 2048); otherwise `hslots` (2048
+// or 4096) as requested.
+int beam_table_slots(int ef, bool search, int hslots, int nch) {
   if (search || ef > 128) return 4096;
+  if (hslots == 1024) return ef <= 64 && nch == 1 ? 1024 : 2048;
   return hslots == 2048 ? 2048 : 4096;
 }
 

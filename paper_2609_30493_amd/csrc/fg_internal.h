@@ -15,7 +15,7 @@ namespace fg {
 constexpr int kHashSlotsMax = 4096;      // LDS visited table per wave (largest variant)
 constexpr int kEcap = kHashSlotsMax / 2; // expanded entries per search (buffer size)
 constexpr int kSpillCap = 8192;          // ids remembered for clearing the spill bitset
-constexpr int kMaxWaveSlots = 2048;      // persistent grid bound (wave slots)
+constexpr int kMaxWaveSlots = 4096;      // persistent grid bound (wave slots)
 constexpr int kMaxEfHarvest = 256;
 constexpr int kMaxEfSearch = 512;
 
@@ -34,7 +34,8 @@ bool make_shape(const fg_data* d, Shape* s);  // validates, sets error
 // beam_table_slots() the size the chosen kernel really uses.
 // screen (ScreenKind) selects the screened harvest kernels (fg_beam_sbf16.hip,
 // fg_beam_sfp8.hip: float32 rows of more than 16 chunks only).
-int beam_table_slots(int ef, bool search, int hslots);
+int beam_table_slots(int ef, bool search, int hslots, int nch);
+int beam_chunks_per_lane(const Shape& s);  // NCH of the kernel the dispatch picks
 int beam_grid(const Shape& s, int ef, bool search, int hslots, int screen = SCR_NONE, int waves_per_cu = 0);
 hipError_t launch_beam(const Shape& s, BeamArgs& a, bool search, int grid, int hslots, hipStream_t st,
                        int screen = SCR_NONE);
