@@ -98,6 +98,7 @@ struct WsMap {
   size_t off[2], ids[2], rows, cnt, tparent, roots;  // the whole build
   size_t sat;
   size_t xs, xs_err, xs_norm, xs_sinv;      // screened harvest (last: only they depend on d)
+  size_t gram;                              // Gram-tile prune scratch (float32, d > 256)
   int64_t xs_stride;
   SatWs satw;
   size_t total;
@@ -153,6 +154,7 @@ WsMap ws_map(int64_t n, const fg_params* p, int d = 0) {
   m.roots = take(64 * 4);
   sat_workspace_bytes(n, (uint32_t)T, &m.satw);
   m.sat = take(m.satw.total);
+  if (p && d > 256 && d % 4 == 0 && d <= 1024) m.gram = take((size_t)kGramSlots * kGramMax * kGramMax * 4);
   if (p && p->screen && d > 0) {
     m.xs_stride = screen_stride(d, (int)p->screen);
     m.xs = take(un * (uint64_t)m.xs_stride);
@@ -167,7 +169,7 @@ WsMap ws_map(int64_t n, const fg_params* p, int d = 0) {
 // ctl region: [0] queue, [1..4] beam counters, [8] status (int)
 struct Ctl {
   unsigned long long queue;
-  unsigned long long counters[5];    // beam: evals, expansions, prune pairs, spilled, screen-rejected
+  unsigned long long counters[6];    // beam: evals, expansions, prune pairs, spilled, screen-rejected, rechecks
   unsigned long long fin[2];         // finalize: candidate distances, prune pairs
   uint32_t nbig, pad32;              // rows sent to the big-row paths
   int status;                        // 1 expanded-set overflow
@@ -244,6 +246,10 @@ fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* id
   a.counters = ctl->counters;
   a.status = &ctl->status;
   a.d = s.d;
+  if (m.gram && s.dk != U8L2 && s.Q > 64) {
+    a.gram = reinterpret_cast<float*>(at(ws, m.gram));
+    grid = grid < kGramSlots ? grid : kGramSlots;
+  }
   if (bi) {
     a.inst_of = bi->inst_of;
     a.inst_roots = bi->inst_roots;
@@ -518,6 +524,7 @@ fg_status fg_harvest_block(const fg_data* data, const fg_csr* Sb, const uint32_t
     counters->prune_evals += c.counters[2];
     counters->spilled_queries += c.counters[3];
     counters->screen_rejected += c.counters[4];
+    counters->prune_rechecks += c.counters[5];
     return status_error(c.status);
   }
   return FG_OK;
@@ -822,6 +829,7 @@ fg_status fg_build_graph(const fg_data* data, uint64_t seed, const fg_params* pa
     counters->prune_evals += c.counters[2];
     counters->spilled_queries += c.counters[3];
     counters->screen_rejected += c.counters[4];
+    counters->prune_rechecks += c.counters[5];
     counters->finalize_evals += c.fin[0] + c.fin[1];
   }
   if (timings) {

@@ -98,7 +98,7 @@ struct BeamArgs {
   int64_t spill_words;
   uint32_t* spill_list;
   int spill_cap;
-  unsigned long long* counters;  // evals, expansions, prune pairs, spilled, screen-rejected
+  unsigned long long* counters;  // evals, expansions, prune pairs, spilled, screen-rejected, prune rechecks
   int* status;                   // bit 0: expanded-list overflow
   // screened harvest: the narrow copy (row stride xs_stride bytes, the
   // elements in data order), per row the norm of its quantisation error
@@ -116,7 +116,13 @@ struct BeamArgs {
   const uint16_t* inst_of;
   const uint32_t* inst_roots;
   const int* inst_ef;
+  // float32 rows of more than 64 chunks: per wave slot a kGramMax^2 float
+  // scratch for the candidates' Gram matrix (NULL: exact prune only)
+  float* gram;
 };
+
+constexpr int kGramMax = 256;    // candidates the Gram-tile prune takes
+constexpr int kGramSlots = 2048; // wave slots that have Gram scratch
 
 enum ScreenKind { SCR_NONE = 0, SCR_BF16 = 1, SCR_FP8 = 2 };
 
@@ -381,10 +387,241 @@ __device__ int prune_wave(const RowSet& X, float alpha, int R, const uint64_t* s
 // Waves per SIMD the register budget aims at: more searches in flight hide
 // more gather latency.  Four for one-chunk rows with the 1024-slot table
 // (9 KB of LDS per wave), three for rows of one or two chunks per lane,
-// else whatever the registers allow.
+// two for the longest rows, else whatever the registers allow.
 template <int NCH, int HS>
 constexpr int beam_waves_per_eu() {
-  return (NCH == 1 && HS == 1024) ? 4 : (NCH <= 2 ? 3 : 1);
+  return (NCH == 1 && HS == 1024) ? 4 : (NCH <= 2 ? 3 : (NCH >= 16 ? 2 : 1));
+}
+
+// ------------------------------------------------------------ Gram-tile prune
+// Float32 rows of more than 64 chunks: the occlusion prune's pair distances
+// come from the candidates' Gram matrix on matrix cores (each candidate row
+// read once per 32-row block instead of once per kept candidate),
+// d~(a,c) = G_aa + G_cc - 2 G_ac (cosine: 1 - G_ac).  A test whose outcome
+// the rounding margin cannot settle is recomputed exactly in the declared
+// order, so the kept lists and the pair count are those of prune_wave.
+
+typedef float gram_f32x16 __attribute__((ext_vector_type(16)));
+
+// Row of the 32x32 accumulator held in register r of lane l.
+__device__ __forceinline__ int gram_acc_row(int r, int lane) { return (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3); }
+
+// G[i * kGramMax + j] = <c_i, c_j> for j >= i, candidates c_i = row of sk[i].
+// Lanes l and l+32 read chunks c and c+1 of the same row: the four elements
+// of each 16-byte chunk are four k-steps of the 32x32x2 product.  Rows past
+// mc read candidate 0 (in bounds; their results are not stored), so the
+// loop has no per-lane branches and keeps kGramPF chunk pairs in flight.
+constexpr int kGramPF = 4;
+
+__device__ __forceinline__ void gram_mfma4(gram_f32x16& acc, const float4& a, const float4& b) {
+  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.z, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b.w, acc, 0, 0, 0);
+}
+
+__device__ __forceinline__ void gram_tiles(const RowSet& X, const uint64_t* sk, int mc, float* G) {
+  const int lane = lane_id();
+  const int nb = (mc + 31) / 32;
+  const int Q = X.Q;
+  const int Qe = Q & ~1;  // chunks read in pairs; an odd last chunk is done apart
+  const int h = lane >> 5;
+  for (int I = 0; I < nb; I++) {
+    const int ra = 32 * I + (lane & 31);
+    const uint8_t* pa = X.x + (size_t)key_id(sk[ra < mc ? ra : 0]) * X.stride + 16 * h;
+    for (int J = I; J < nb; J++) {
+      const int rb = 32 * J + (lane & 31);
+      const uint8_t* pb = X.x + (size_t)key_id(sk[rb < mc ? rb : 0]) * X.stride + 16 * h;
+      gram_f32x16 acc;
+#pragma unroll
+      for (int e = 0; e < 16; e++) acc[e] = 0.0f;
+      float4 fa[kGramPF], fb[kGramPF];
+#pragma unroll
+      for (int u = 0; u < kGramPF; u++)
+        if (2 * u < Qe) {
+          fa[u] = *reinterpret_cast<const float4*>(pa + 32 * (size_t)u);
+          fb[u] = *reinterpret_cast<const float4*>(pb + 32 * (size_t)u);
+        }
+      int c = 0;
+      for (; c + 2 * kGramPF <= Qe; c += 2 * kGramPF) {
+#pragma unroll
+        for (int u = 0; u < kGramPF; u++) {
+          gram_mfma4(acc, fa[u], fb[u]);
+          const int nx = c + 2 * (u + kGramPF);
+          if (nx < Qe) {
+            fa[u] = *reinterpret_cast<const float4*>(pa + 16 * (size_t)nx);
+            fb[u] = *reinterpret_cast<const float4*>(pb + 16 * (size_t)nx);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kGramPF; u++)
+        if (c + 2 * u < Qe) gram_mfma4(acc, fa[u], fb[u]);
+      if (Q & 1) {  // the last chunk: lanes of the upper half contribute zero
+        float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f), b = a;
+        if (h == 0) {
+          a = *reinterpret_cast<const float4*>(pa + 16 * (size_t)Qe);
+          b = *reinterpret_cast<const float4*>(pb + 16 * (size_t)Qe);
+        }
+        gram_mfma4(acc, a, b);
+      }
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        const int i = 32 * I + gram_acc_row(r, lane);
+        const int j = 32 * J + (lane & 31);
+        if (i < mc && j < mc && j >= i) G[i * kGramMax + j] = acc[r];
+      }
+    }
+  }
+}
+
+// Margin for d~ against the exact declared-order distance (standard model:
+// every elementary operation of the matrix-core sum is taken to err by up to
+// 2^-23 relative, twice the float32 unit roundoff, since its internal order
+// and rounding are the hardware's; the declared order errs by gc):
+//   squared L2: |d~ - d| <= (gg + 2u)(1 + gg) (|a| + |c|)^2, with
+//     (|a| + |c|)^2 <= 2 (G_aa + G_cc) / (1 - gg); the exact value adds
+//     gc (|d~| + that);
+//   cosine: |G_ac - <a,c>| <= gg |a||c|, the declared order gc |a||c|, two
+//     roundings of 1 - s at most 2u (1 + |a||c|) each, |a||c| <=
+//     sqrt(G_aa G_cc) / (1 - gg).
+// The result is doubled.
+template <int DK>
+__device__ __forceinline__ float gram_eps(float dt, float gaa, float gcc, int d) {
+  const float u = 5.9604645e-08f;  // 2^-24
+  const float gg = (d + 4) * (2.0f * u) / (1.0f - (d + 4) * (2.0f * u));
+  const float gc = (d / 16 + 8) * u / (1.0f - (d / 16 + 8) * u);
+  float eps;
+  if constexpr (DK == F32L2) {
+    const float s2 = 2.0f * (fabsf(gaa) + fabsf(gcc)) / (1.0f - gg);
+    const float b = (gg + 2.0f * u) * (1.0f + gg) * s2;
+    eps = b + gc * (fabsf(dt) + b);
+  } else {
+    const float nn = __builtin_sqrtf(fabsf(gaa) * fabsf(gcc)) / (1.0f - gg);
+    eps = (gg + gc) * nn + 4.0f * u * (1.0f + nn);
+  }
+  return 2.0f * eps;
+}
+
+// Exact declared-order float32 distance between two rows read chunk by
+// chunk (the same partial slots, tree and cross-lane levels as group_dist,
+// so the same bits, without holding either row in registers).
+template <int DK, int L, int NCH>
+__device__ __forceinline__ float group_dist_stream(const uint8_t* ra, const uint8_t* rb, int Q, int g) {
+  constexpr int S = 16 / L;
+  float p[S];
+#pragma unroll
+  for (int s = 0; s < S; s++) p[s] = 0.0f;
+#pragma unroll 4
+  for (int i = 0; i < NCH; i++) {
+    const int q = g + L * i;
+    if (q < Q) {
+      float& acc = p[i % S];
+      const float4 xa = *reinterpret_cast<const float4*>(ra + 16 * (size_t)q);
+      const float4 xb = *reinterpret_cast<const float4*>(rb + 16 * (size_t)q);
+      if constexpr (DK == F32L2) {
+        const float d0 = xa.x - xb.x, d1 = xa.y - xb.y, d2 = xa.z - xb.z, d3 = xa.w - xb.w;
+        acc = __builtin_fmaf(d0, d0, acc);
+        acc = __builtin_fmaf(d1, d1, acc);
+        acc = __builtin_fmaf(d2, d2, acc);
+        acc = __builtin_fmaf(d3, d3, acc);
+      } else {
+        acc = __builtin_fmaf(xa.x, xb.x, acc);
+        acc = __builtin_fmaf(xa.y, xb.y, acc);
+        acc = __builtin_fmaf(xa.z, xb.z, acc);
+        acc = __builtin_fmaf(xa.w, xb.w, acc);
+      }
+    }
+  }
+#pragma unroll
+  for (int off = S / 2; off >= 1; off >>= 1)
+#pragma unroll
+    for (int s = 0; s < off; s++) p[s] = p[s] + p[s + off];
+  float v = p[0];
+#pragma unroll
+  for (int off = L / 2; off >= 1; off >>= 1) v = v + __shfl_xor(v, off, 64);
+  if constexpr (DK == F32COS) v = 1.0f - v;
+  return v;
+}
+
+// The greedy prune of prune_wave, its pair tests decided from the Gram
+// matrix (gram_tiles, then a fence) where the margin allows.  G is this
+// wave's kGramMax^2 scratch; *rc counts the exact recomputations.
+template <int DK, int L, int NCH>
+__device__ int prune_gram(const RowSet& X, int d, float alpha, int R, const uint64_t* sk, int mc, const float* G,
+                          uint32_t* alive, uint32_t* cid, uint64_t* ckey, uint32_t* out, unsigned long long* pe,
+                          unsigned long long* rc) {
+  const int lane = lane_id();
+  const int g = lane % L;
+  for (int w = lane; w < (mc + 31) / 32; w += 64) {
+    int valid = mc - w * 32;
+    alive[w] = valid >= 32 ? 0xFFFFFFFFu : ((1u << valid) - 1u);
+  }
+  wave_sync();
+  const float u8 = 8.0f * 5.9604645e-08f;
+  int kept = 0, i = 0;
+  while (kept < R) {
+    int nxt = -1;
+    for (int base = i & ~63; base < mc; base += 64) {
+      int j = base + lane;
+      bool live = j >= i && j < mc && ((alive[j >> 5] >> (j & 31)) & 1u);
+      uint64_t m = ballot(live);
+      if (m) {
+        nxt = base + __ffsll((long long)m) - 1;
+        break;
+      }
+    }
+    if (nxt < 0) break;
+    i = nxt;
+    uint32_t kid = key_id(sk[i]);
+    if (lane == 0) out[kept] = kid;
+    kept++;
+    if (kept == R) break;
+    const float gaa = G[i * kGramMax + i];
+    const uint8_t* krow = X.x + (size_t)kid * X.stride;
+    for (int base = i + 1; base < mc; base += 64) {
+      int j = base + lane;
+      bool live = j < mc && ((alive[j >> 5] >> (j & 31)) & 1u);
+      uint64_t m = ballot(live);
+      int nl = popc64(m);
+      if (nl == 0) continue;
+      *pe += (unsigned long long)nl;
+      bool kill = false, unsure = false;
+      float dpc = 0.0f;
+      if (live) {
+        dpc = hi_to_float<DK>(key_hi(sk[j]));
+        const float gcc = G[j * kGramMax + j], gac = G[i * kGramMax + j];
+        const float dt = DK == F32L2 ? (gaa + gcc) - 2.0f * gac : 1.0f - gac;
+        const float eps = gram_eps<DK>(dt, gaa, gcc, d);
+        // bounds on fl(alpha * exact), widened for their own roundings
+        const float up = alpha * (dt + eps), lo = alpha * (dt - eps);
+        if (up + fabsf(up) * u8 < dpc) kill = true;
+        else if (!(lo - fabsf(lo) * u8 > dpc)) unsure = true;
+      }
+      const uint64_t mu = ballot(unsure);
+      const int nu = popc64(mu);
+      if (nu) {  // exact distances for the tests the margin left open
+        *rc += (unsigned long long)nu;
+        const int pos = popc64(mu & lanes_below());
+        if (unsure) cid[pos] = key_id(sk[j]);
+        wave_sync();
+        constexpr int G4 = 64 / L;
+        float* cd = reinterpret_cast<float*>(ckey);
+        for (int r0 = 0; r0 < nu; r0 += G4) {
+          const int r = r0 + lane / L;
+          const uint32_t cu = cid[r < nu ? r : 0];
+          const float v = group_dist_stream<DK, L, NCH>(krow, X.x + (size_t)cu * X.stride, X.Q, g);
+          if (r < nu && g == 0) cd[r] = v;
+        }
+        wave_sync();
+        if (unsure) kill = alpha * cd[pos] <= dpc;
+      }
+      if (kill) atomicAnd(&alive[j >> 5], ~(1u << (j & 31)));
+      wave_sync();
+    }
+    i++;
+  }
+  return kept;
 }
 
 template <int DK, int L, int NCH, int EFMAX, int HSLOTS, bool SEARCH, int SCR = SCR_NONE>
@@ -403,7 +640,7 @@ k_beam(BeamArgs A) {
   constexpr int kRB = (NCH >= 16) ? 1 : (NCH == 1 ? (HSLOTS == 1024 ? 8 : 12) : 16 / NCH);
   const RowSet X{A.x, A.stride, A.Q};
 
-  unsigned long long my_evals = 0, my_exp = 0, my_pe = 0, my_spilled = 0, my_rej = 0;
+  unsigned long long my_evals = 0, my_exp = 0, my_pe = 0, my_spilled = 0, my_rej = 0, my_rc = 0;
 #ifdef FG_PROFILE
   unsigned long long prof[16] = {};
 #endif
@@ -616,7 +853,21 @@ k_beam(BeamArgs A) {
         int mc = 0;
         for (int base = 0; base < M; base += 64) mc += popc64(ballot(sk[base + lane] != FG_KEY_NONE));
         FG_TICK(5);
-        kept = prune_wave<DK, L, NCH>(X, A.alpha, A.R, sk, mc, S.alive, S.cid, S.ckey, out, &my_pe);
+        bool gram = false;
+        if constexpr (DK != U8L2 && NCH >= 16)
+          gram = A.gram != nullptr && mc <= kGramMax && wslot < kGramSlots;
+        if (gram) {
+          float* G = A.gram + (size_t)wslot * kGramMax * kGramMax;
+          gram_tiles(X, sk, mc, G);
+          // the tiles were written by other lanes, and this slot's scratch
+          // may sit in the vector L1 from an earlier search: make the
+          // stores visible and drop stale lines before reading them back
+          __threadfence();
+          FG_TICK(8);
+          kept = prune_gram<DK, L, NCH>(X, A.d, A.alpha, A.R, sk, mc, G, S.alive, S.cid, S.ckey, out, &my_pe,
+                                        &my_rc);
+        } else
+          kept = prune_wave<DK, L, NCH>(X, A.alpha, A.R, sk, mc, S.alive, S.cid, S.ckey, out, &my_pe);
         FG_TICK(4);
       }
       for (int t = kept + lane; t < A.R; t += 64) out[t] = FG_NONE;
@@ -643,13 +894,14 @@ k_beam(BeamArgs A) {
   }
   if (lane == 0) {
 #ifdef FG_PROFILE
-    for (int i = 0; i < 8; i++) atomicAdd(&fg_prof_cycles[i], prof[i]);
+    for (int i = 0; i < 9; i++) atomicAdd(&fg_prof_cycles[i], prof[i]);
 #endif
     atomicAdd(&A.counters[0], my_evals);
     atomicAdd(&A.counters[1], my_exp);
     atomicAdd(&A.counters[2], my_pe);
     atomicAdd(&A.counters[3], my_spilled);
     if (my_rej) atomicAdd(&A.counters[4], my_rej);
+    if (my_rc) atomicAdd(&A.counters[5], my_rc);
   }
 }
 

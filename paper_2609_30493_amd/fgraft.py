@@ -57,7 +57,7 @@ class fg_counters(C.Structure):
     _fields_ = [("scaffold_evals", C.c_uint64), ("harvest_evals", C.c_uint64),
                 ("prune_evals", C.c_uint64), ("expansions", C.c_uint64),
                 ("finalize_evals", C.c_uint64), ("spilled_queries", C.c_uint64),
-                ("screen_rejected", C.c_uint64)]
+                ("screen_rejected", C.c_uint64), ("prune_rechecks", C.c_uint64)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
