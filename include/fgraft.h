@@ -145,9 +145,10 @@ typedef struct {
   uint64_t finalize_evals;
   uint64_t spilled_queries; /* searches whose visited set left on-chip memory */
   uint64_t screen_rejected; /* harvest evaluations settled by the screen alone (included in harvest_evals) */
-  uint64_t prune_rechecks;  /* prune pair tests (of prune_evals) that float32 rows longer than 256
-                               elements settled by an exact recomputation: the matrix-core
-                               distance's margin left them open */
+  uint64_t prune_rechecks;  /* pair tests of the harvest and finalize prunes (counted in
+                               prune_evals / finalize_evals) that, for float32 rows longer than
+                               256 elements, the matrix-core distance's margin left open and an
+                               exact recomputation settled */
 } fg_counters;
 
 /* Per-phase device time (HIP events on `stream`), milliseconds. */

@@ -170,7 +170,7 @@ WsMap ws_map(int64_t n, const fg_params* p, int d = 0) {
 struct Ctl {
   unsigned long long queue;
   unsigned long long counters[6];    // beam: evals, expansions, prune pairs, spilled, screen-rejected, rechecks
-  unsigned long long fin[2];         // finalize: candidate distances, prune pairs
+  unsigned long long fin[3];         // finalize: candidate distances, prune pairs, exact rechecks
   uint32_t nbig, pad32;              // rows sent to the big-row paths
   int status;                        // 1 expanded-set overflow
 };
@@ -391,6 +391,8 @@ fg_status finalize_launch(const Shape& s, const uint32_t* rows, const uint32_t* 
   f.g_nbrs = g_nbrs;
   f.g_cnt = g_cnt;
   f.counters = ctl->fin;
+  f.d = s.d;
+  f.gram = (m.gram && s.dk != U8L2 && s.Q > 64) ? reinterpret_cast<float*>(at(ws, m.gram)) : nullptr;
   f.status = &ctl->status;
   f.big = reinterpret_cast<uint32_t*>(at(ws, m.big));
   f.nbig = &ctl->nbig;
@@ -524,7 +526,7 @@ fg_status fg_harvest_block(const fg_data* data, const fg_csr* Sb, const uint32_t
     counters->prune_evals += c.counters[2];
     counters->spilled_queries += c.counters[3];
     counters->screen_rejected += c.counters[4];
-    counters->prune_rechecks += c.counters[5];
+    counters->prune_rechecks += c.counters[5] + c.fin[2];
     return status_error(c.status);
   }
   return FG_OK;
@@ -627,6 +629,7 @@ fg_status fg_finalize(const fg_data* data, const uint32_t* rows_dev, const uint3
     r = read_ctl(ws_dev, m, st, &c);
     if (r) return r;
     counters->finalize_evals += c.fin[0] + c.fin[1];
+    counters->prune_rechecks += c.fin[2];
     return status_error(c.status);
   }
   return FG_OK;
@@ -829,7 +832,7 @@ fg_status fg_build_graph(const fg_data* data, uint64_t seed, const fg_params* pa
     counters->prune_evals += c.counters[2];
     counters->spilled_queries += c.counters[3];
     counters->screen_rejected += c.counters[4];
-    counters->prune_rechecks += c.counters[5];
+    counters->prune_rechecks += c.counters[5] + c.fin[2];
     counters->finalize_evals += c.fin[0] + c.fin[1];
   }
   if (timings) {

@@ -22,7 +22,7 @@ __global__ void __launch_bounds__(64) k_finalize(FinalizeArgs A) {
   __shared__ uint64_t ckey[64];
   const int lane = lane_id();
   const int g = lane % L;
-  unsigned long long ev = 0, pe = 0;
+  unsigned long long ev = 0, pe = 0, rcheck = 0;
   for (int64_t p = blockIdx.x; p < A.n; p += gridDim.x) {
     uint32_t* out = A.g_nbrs + p * A.R;
     const int c = (int)min(A.cnt[p], (uint32_t)A.R);  // counts above R are not trusted
@@ -74,7 +74,16 @@ __global__ void __launch_bounds__(64) k_finalize(FinalizeArgs A) {
     wave_sort_lds<uint64_t>(sk, Mk);
     int kept;
     if (m > A.R || A.reprune_all) {
-      kept = prune_wave<DK, L, NCH>(A.X, A.alpha, A.R, sk, m, alive, cid, ckey, out, &pe);
+      bool gram = false;
+      if constexpr (DK != U8L2 && NCH >= 16) gram = A.gram != nullptr && m <= kGramMax && blockIdx.x < kGramSlots;
+      if (gram) {  // matrix-core pair distances with exact rechecks (see prune_gram)
+        float* G = A.gram + (size_t)blockIdx.x * kGramMax * kGramMax;
+        gram_tiles(A.X, sk, m, G);
+        __threadfence();
+        kept = prune_gram<DK, L, NCH>(A.X, A.d, A.alpha, A.R, sk, m, G, alive, cid, ckey, out, &pe, &rcheck);
+      } else {
+        kept = prune_wave<DK, L, NCH>(A.X, A.alpha, A.R, sk, m, alive, cid, ckey, out, &pe);
+      }
     } else {
       for (int i = lane; i < m; i += 64) out[i] = key_id(sk[i]);
       kept = m;
@@ -86,6 +95,7 @@ __global__ void __launch_bounds__(64) k_finalize(FinalizeArgs A) {
   if (lane == 0) {
     atomicAdd(&A.counters[0], ev);
     atomicAdd(&A.counters[1], pe);
+    if (rcheck) atomicAdd(&A.counters[2], rcheck);
   }
 }
 
@@ -212,6 +222,7 @@ __global__ void __launch_bounds__(64) k_fin_big_prune(FinalizeArgs A, const KSeg
 template <int DK, int L, int NCH>
 hipError_t go(const FinalizeArgs& a, const FinalizeBig& big, hipStream_t st) {
   int grid = (int)(a.n < 65536 ? a.n : 65536);
+  if (a.gram && grid > kGramSlots) grid = kGramSlots;  // one Gram scratch per block
   k_finalize<DK, L, NCH><<<grid, 64, 0, st>>>(a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -111,10 +111,12 @@ struct FinalizeArgs {
   const uint32_t* rev;
   uint32_t* g_nbrs;
   uint32_t* g_cnt;
-  unsigned long long* counters;  // [0] candidate distances, [1] prune pairs
+  unsigned long long* counters;  // [0] candidate distances, [1] prune pairs, [2] exact rechecks
   int* status;
   uint32_t* big;   // points whose candidates exceed the on-chip bound
   uint32_t* nbig;  // their count (device, zero on entry)
+  int d;
+  float* gram;     // float32 rows longer than 256 elements: Gram scratch per block (or NULL)
 };
 struct FinalizeBig {
   KSeg* segs;
