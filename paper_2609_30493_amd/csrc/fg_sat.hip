@@ -328,18 +328,31 @@ __global__ void __launch_bounds__(64) k_sat_assign(SatArgs A) {
 }
 
 // Count the members of each child bag.
+// Bags with at most kBinMax children count (and, in k_sat_scatter, rank)
+// their rejected points per child in LDS first, so a tile adds to each
+// child's global counter once; the top levels have few children and would
+// otherwise serialise millions of atomics on a handful of counters.
+constexpr int kBinMax = 1024;
+
 __global__ void __launch_bounds__(64) k_sat_count(SatArgs A) {
+  __shared__ uint32_t bins[kBinMax];
   const int lane = lane_id();
   const SatTile tl = A.tiles[blockIdx.x];
   const SatSeg sg = A.segs[tl.seg];
   const uint32_t hi = min(sg.len, tl.off + kTile);
+  if (sg.nN > (uint32_t)kBinMax) {
+    for (uint32_t j = tl.off + lane; j < hi; j += 64)
+      if (A.flag[sg.start + j] == 2) atomicAdd(&A.ccount[sg.start + A.owner[sg.start + j]], 1u);
+    return;
+  }
+  for (uint32_t k = lane; k < sg.nN; k += 64) bins[k] = 0;
+  wave_sync();
   for (uint32_t j = tl.off + lane; j < hi; j += 64)
-    if (A.flag[sg.start + j] == 2) atomicAdd(&A.ccount[sg.start + A.owner[sg.start + j]], 1u);
+    if (A.flag[sg.start + j] == 2) atomicAdd(&bins[A.owner[sg.start + j]], 1u);
+  wave_sync();
+  for (uint32_t k = lane; k < sg.nN; k += 64)
+    if (bins[k]) atomicAdd(&A.ccount[sg.start + k], bins[k]);
 }
-
-// One wave per large bag: offsets of the child bags, parents, the new
-// segments (large ones for the next level, small ones for the subtree
-// builder), and the neighbours' final slots.
 __global__ void __launch_bounds__(64) k_sat_children(SatArgs A) {
   const int lane = lane_id();
   const SatSeg sg = A.segs[blockIdx.x];
@@ -385,18 +398,47 @@ __global__ void __launch_bounds__(64) k_sat_children(SatArgs A) {
 }
 
 __global__ void __launch_bounds__(64) k_sat_scatter(SatArgs A) {
+  __shared__ uint32_t bins[kBinMax];
   const int lane = lane_id();
   const SatTile tl = A.tiles[blockIdx.x];
   const SatSeg sg = A.segs[tl.seg];
   const uint32_t hi = min(sg.len, tl.off + kTile);
-  for (uint32_t j = tl.off + lane; j < hi; j += 64) {
-    if (A.flag[sg.start + j] != 2) continue;
-    uint32_t k = A.owner[sg.start + j];
-    uint32_t at = atomicAdd(&A.ccount[sg.start + k], 1u);
-    A.perm2[sg.start + sg.nN + A.coff[sg.start + k] + at] = A.perm[sg.start + j];
+  if (sg.nN > (uint32_t)kBinMax) {
+    for (uint32_t j = tl.off + lane; j < hi; j += 64) {
+      if (A.flag[sg.start + j] != 2) continue;
+      uint32_t k = A.owner[sg.start + j];
+      uint32_t at = atomicAdd(&A.ccount[sg.start + k], 1u);
+      A.perm2[sg.start + sg.nN + A.coff[sg.start + k] + at] = A.perm[sg.start + j];
+    }
+    return;
+  }
+  // a bag's order does not matter: the next level sorts it by (distance, id)
+  constexpr int kPer = kTile / 64;
+  uint32_t rank[kPer], own[kPer];
+  for (uint32_t k = lane; k < sg.nN; k += 64) bins[k] = 0;
+  wave_sync();
+#pragma unroll
+  for (int it = 0; it < kPer; it++) {
+    const uint32_t j = tl.off + it * 64 + lane;
+    own[it] = FG_NONE;
+    if (j < hi && A.flag[sg.start + j] == 2) {
+      own[it] = A.owner[sg.start + j];
+      rank[it] = atomicAdd(&bins[own[it]], 1u);
+    }
+  }
+  wave_sync();
+  for (uint32_t k = lane; k < sg.nN; k += 64)
+    if (bins[k]) bins[k] = atomicAdd(&A.ccount[sg.start + k], bins[k]);
+  wave_sync();
+#pragma unroll
+  for (int it = 0; it < kPer; it++) {
+    const uint32_t j = tl.off + it * 64 + lane;
+    if (own[it] != FG_NONE) {
+      const uint32_t k = own[it];
+      A.perm2[sg.start + sg.nN + A.coff[sg.start + k] + bins[k] + rank[it]] = A.perm[sg.start + j];
+    }
   }
 }
-
 __global__ void __launch_bounds__(64) k_sat_copy_back(SatArgs A) {
   const int lane = lane_id();
   const SatTile tl = A.tiles[blockIdx.x];
