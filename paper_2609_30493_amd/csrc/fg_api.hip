@@ -92,7 +92,7 @@ int table_request(const fg_params* p) {
 struct WsMap {
   size_t ctl, bits, slist, ebuf;            // beam kernels
   size_t deg, cursor, newlen, aoff, noff, zoff, addbuf, tmp, scan;  // edge lists / merges
-  size_t keys, keys2, uni, big, ksegs, ktiles;  // rows too large for on-chip sorting
+  size_t keys, keys2, uni, big, mid, ksegs, ktiles;  // rows too large for on-chip sorting
   size_t ktile_cap;
   size_t sgoff, sgids;                      // search graph
   size_t off[2], ids[2], rows, cnt, tparent, roots;  // the whole build
@@ -139,6 +139,7 @@ WsMap ws_map(int64_t n, const fg_params* p, int d = 0) {
   m.keys2 = take(m.add_cap * 8);
   m.uni = take(m.add_cap * 4);
   m.big = take(un * 4);
+  m.mid = take(un * 4);
   m.ksegs = take(un * sizeof(KSeg));
   m.ktile_cap = m.add_cap / kSegTilePositions + un + 64;
   m.ktiles = take(m.ktile_cap * sizeof(KTile));
@@ -171,7 +172,7 @@ struct Ctl {
   unsigned long long queue;
   unsigned long long counters[6];    // beam: evals, expansions, prune pairs, spilled, screen-rejected, rechecks
   unsigned long long fin[3];         // finalize: candidate distances, prune pairs, exact rechecks
-  uint32_t nbig, pad32;              // rows sent to the big-row paths
+  uint32_t nbig, nmid;               // rows sent to the big-row paths / finalize's second tier
   int status;                        // 1 expanded-set overflow
 };
 
@@ -396,7 +397,9 @@ fg_status finalize_launch(const Shape& s, const uint32_t* rows, const uint32_t* 
   f.status = &ctl->status;
   f.big = reinterpret_cast<uint32_t*>(at(ws, m.big));
   f.nbig = &ctl->nbig;
-  FG_HIP(fill_u32(&ctl->nbig, 0, 1, st));
+  f.mid = reinterpret_cast<uint32_t*>(at(ws, m.mid));
+  f.nmid = &ctl->nmid;
+  FG_HIP(fill_u32(&ctl->nbig, 0, 2, st));  // nbig and nmid
   FinalizeBig fb{reinterpret_cast<KSeg*>(at(ws, m.ksegs)), reinterpret_cast<KTile*>(at(ws, m.ktiles)), m.ktile_cap,
                  reinterpret_cast<uint64_t*>(at(ws, m.keys)), reinterpret_cast<uint64_t*>(at(ws, m.keys2))};
   FG_HIP(launch_finalize(s.dk, s.Q, f, fb, st));

@@ -10,93 +10,130 @@ namespace fg {
 
 namespace {
 
-constexpr int kFinCap = 2048;      // candidates per point held on chip
+constexpr int kFinCap = 2048;      // candidates per point held on chip (second tier)
+constexpr int kFinSmall = 512;     // candidates held by the first tier
 constexpr int kFinKeptMax = 1024;  // R bound of the big-row path
 
+// One point: candidates gathered (ids outside [0, n) dropped), sorted,
+// deduplicated, their distances to p, then sorted by key and pruned when
+// more than R (or always with reprune_all).  m0 <= CAP.
+template <int DK, int L, int NCH, int CAP>
+__device__ void fin_point(const FinalizeArgs& A, int64_t p, uint32_t* cb, uint64_t* sk, uint32_t* alive,
+                          uint32_t* cid, uint64_t* ckey, unsigned long long& ev, unsigned long long& pe,
+                          unsigned long long& rcheck) {
+  const int lane = lane_id();
+  const int g = lane % L;
+  uint32_t* out = A.g_nbrs + p * A.R;
+  const int c = (int)min(A.cnt[p], (uint32_t)A.R);  // counts above R are not trusted
+  const uint64_t r0 = A.revoff[p];
+  const int m0 = c + (int)(A.revoff[p + 1] - r0);
+  int M = 64;
+  while (M < m0) M <<= 1;
+  for (int i = lane; i < M; i += 64) {
+    uint32_t v = i < c ? A.rows[p * A.R + i] : (i < m0 ? A.rev[r0 + (i - c)] : FG_NONE);
+    cb[i] = v < (uint64_t)A.n ? v : FG_NONE;  // ids outside [0, n) are dropped
+  }
+  wave_sync();
+  wave_sort_lds<uint32_t>(cb, M);
+  // keep first occurrences (in place: a chunk is read before it is written)
+  int m = 0;
+  uint32_t carry = FG_NONE;  // last original value of the previous chunk
+  for (int base = 0; base < M; base += 64) {
+    int i = base + lane;
+    uint32_t x = cb[i];
+    uint32_t prev = __shfl(x, lane > 0 ? lane - 1 : 0, 64);
+    if (lane == 0) prev = carry;
+    carry = __shfl(x, 63, 64);
+    bool keep = x != FG_NONE && x != prev;
+    uint64_t msk = ballot(keep);
+    wave_sync();
+    if (keep) cb[m + popc64(msk & lanes_below())] = x;
+    m += popc64(msk);
+    wave_sync();
+  }
+  Chunks<L, NCH> qc;
+  load_chunks<L, NCH>(qc, A.X.x + (size_t)p * A.X.stride, A.X.Q, g);
+  uint32_t qn = 0;
+  if constexpr (DK == U8L2) qn = group_sum_u32<L>(u8_selfdot<L, NCH>(qc));
+  for (int base = 0; base < m; base += 64) {
+    int cnt = m - base < 64 ? m - base : 64;
+    batch_dists_rs<DK, L, NCH>(A.X, qc, qn, cb + base, cnt, sk + base);
+  }
+  ev += (unsigned long long)m;
+  int Mk = 64;
+  while (Mk < m) Mk <<= 1;
+  for (int i = m + lane; i < Mk; i += 64) sk[i] = FG_KEY_NONE;
+  wave_sync();
+  wave_sort_lds<uint64_t>(sk, Mk);
+  int kept;
+  if (m > A.R || A.reprune_all) {
+    bool gram = false;
+    if constexpr (DK != U8L2 && NCH >= 16) gram = A.gram != nullptr && m <= kGramMax && blockIdx.x < kGramSlots;
+    if (gram) {  // matrix-core pair distances with exact rechecks (see prune_gram)
+      float* G = A.gram + (size_t)blockIdx.x * kGramMax * kGramMax;
+      gram_tiles(A.X, sk, m, G);
+      __threadfence();
+      kept = prune_gram<DK, L, NCH>(A.X, A.d, A.alpha, A.R, sk, m, G, alive, cid, ckey, out, &pe, &rcheck);
+    } else {
+      kept = prune_wave<DK, L, NCH>(A.X, A.alpha, A.R, sk, m, alive, cid, ckey, out, &pe);
+    }
+  } else {
+    for (int i = lane; i < m; i += 64) out[i] = key_id(sk[i]);
+    kept = m;
+  }
+  for (int t = kept + lane; t < A.R; t += 64) out[t] = FG_NONE;
+  if (lane == 0) A.g_cnt[p] = (uint32_t)kept;
+  wave_sync();
+}
+
+__device__ __forceinline__ void fin_flush(const FinalizeArgs& A, unsigned long long ev, unsigned long long pe,
+                                          unsigned long long rcheck) {
+  if (lane_id() == 0) {
+    if (ev) atomicAdd(&A.counters[0], ev);
+    if (pe) atomicAdd(&A.counters[1], pe);
+    if (rcheck) atomicAdd(&A.counters[2], rcheck);
+  }
+}
+
+// First tier: one wave per point with at most kFinSmall candidates (small
+// LDS, many waves per compute unit); points with more are listed for the
+// second tier (up to kFinCap) or for the big-row path.
 template <int DK, int L, int NCH>
 __global__ void __launch_bounds__(64) k_finalize(FinalizeArgs A) {
+  __shared__ uint32_t cb[kFinSmall];
+  __shared__ uint64_t sk[kFinSmall];
+  __shared__ uint32_t alive[kFinSmall / 32];
+  __shared__ uint32_t cid[64];
+  __shared__ uint64_t ckey[64];
+  unsigned long long ev = 0, pe = 0, rcheck = 0;
+  for (int64_t p = blockIdx.x; p < A.n; p += gridDim.x) {
+    const int m0 = (int)min(A.cnt[p], (uint32_t)A.R) + (int)(A.revoff[p + 1] - A.revoff[p]);
+    if (m0 > kFinCap) {  // finished by the big-row path
+      if (lane_id() == 0) A.big[atomicAdd(A.nbig, 1u)] = (uint32_t)p;
+      continue;
+    }
+    if (m0 > kFinSmall) {  // finished by the second tier
+      if (lane_id() == 0) A.mid[atomicAdd(A.nmid, 1u)] = (uint32_t)p;
+      continue;
+    }
+    fin_point<DK, L, NCH, kFinSmall>(A, p, cb, sk, alive, cid, ckey, ev, pe, rcheck);
+  }
+  fin_flush(A, ev, pe, rcheck);
+}
+
+// Second tier: the listed points (count read on the device).
+template <int DK, int L, int NCH>
+__global__ void __launch_bounds__(64) k_finalize_mid(FinalizeArgs A) {
   __shared__ uint32_t cb[kFinCap];
   __shared__ uint64_t sk[kFinCap];
   __shared__ uint32_t alive[kFinCap / 32];
   __shared__ uint32_t cid[64];
   __shared__ uint64_t ckey[64];
-  const int lane = lane_id();
-  const int g = lane % L;
   unsigned long long ev = 0, pe = 0, rcheck = 0;
-  for (int64_t p = blockIdx.x; p < A.n; p += gridDim.x) {
-    uint32_t* out = A.g_nbrs + p * A.R;
-    const int c = (int)min(A.cnt[p], (uint32_t)A.R);  // counts above R are not trusted
-    const uint64_t r0 = A.revoff[p];
-    const int rc = (int)(A.revoff[p + 1] - r0);
-    const int m0 = c + rc;
-    if (m0 > kFinCap) {  // finished by the big-row path
-      if (lane == 0) A.big[atomicAdd(A.nbig, 1u)] = (uint32_t)p;
-      continue;
-    }
-    int M = 64;
-    while (M < m0) M <<= 1;
-    for (int i = lane; i < M; i += 64)
-    {
-      uint32_t v = i < c ? A.rows[p * A.R + i] : (i < m0 ? A.rev[r0 + (i - c)] : FG_NONE);
-      cb[i] = v < (uint64_t)A.n ? v : FG_NONE;  // ids outside [0, n) are dropped
-    }
-    wave_sync();
-    wave_sort_lds<uint32_t>(cb, M);
-    // keep first occurrences (in place: a chunk is read before it is written)
-    int m = 0;
-    uint32_t carry = FG_NONE;  // last original value of the previous chunk
-    for (int base = 0; base < M; base += 64) {
-      int i = base + lane;
-      uint32_t x = cb[i];
-      uint32_t prev = __shfl(x, lane > 0 ? lane - 1 : 0, 64);
-      if (lane == 0) prev = carry;
-      carry = __shfl(x, 63, 64);
-      bool keep = x != FG_NONE && x != prev;
-      uint64_t msk = ballot(keep);
-      wave_sync();
-      if (keep) cb[m + popc64(msk & lanes_below())] = x;
-      m += popc64(msk);
-      wave_sync();
-    }
-    Chunks<L, NCH> qc;
-    load_chunks<L, NCH>(qc, A.X.x + (size_t)p * A.X.stride, A.X.Q, g);
-    uint32_t qn = 0;
-    if constexpr (DK == U8L2) qn = group_sum_u32<L>(u8_selfdot<L, NCH>(qc));
-    for (int base = 0; base < m; base += 64) {
-      int cnt = m - base < 64 ? m - base : 64;
-      batch_dists_rs<DK, L, NCH>(A.X, qc, qn, cb + base, cnt, sk + base);
-    }
-    ev += (unsigned long long)m;
-    int Mk = 64;
-    while (Mk < m) Mk <<= 1;
-    for (int i = m + lane; i < Mk; i += 64) sk[i] = FG_KEY_NONE;
-    wave_sync();
-    wave_sort_lds<uint64_t>(sk, Mk);
-    int kept;
-    if (m > A.R || A.reprune_all) {
-      bool gram = false;
-      if constexpr (DK != U8L2 && NCH >= 16) gram = A.gram != nullptr && m <= kGramMax && blockIdx.x < kGramSlots;
-      if (gram) {  // matrix-core pair distances with exact rechecks (see prune_gram)
-        float* G = A.gram + (size_t)blockIdx.x * kGramMax * kGramMax;
-        gram_tiles(A.X, sk, m, G);
-        __threadfence();
-        kept = prune_gram<DK, L, NCH>(A.X, A.d, A.alpha, A.R, sk, m, G, alive, cid, ckey, out, &pe, &rcheck);
-      } else {
-        kept = prune_wave<DK, L, NCH>(A.X, A.alpha, A.R, sk, m, alive, cid, ckey, out, &pe);
-      }
-    } else {
-      for (int i = lane; i < m; i += 64) out[i] = key_id(sk[i]);
-      kept = m;
-    }
-    for (int t = kept + lane; t < A.R; t += 64) out[t] = FG_NONE;
-    if (lane == 0) A.g_cnt[p] = (uint32_t)kept;
-    wave_sync();
-  }
-  if (lane == 0) {
-    atomicAdd(&A.counters[0], ev);
-    atomicAdd(&A.counters[1], pe);
-    if (rcheck) atomicAdd(&A.counters[2], rcheck);
-  }
+  const uint32_t nm = *A.nmid;
+  for (uint32_t k = blockIdx.x; k < nm; k += gridDim.x)
+    fin_point<DK, L, NCH, kFinCap>(A, A.mid[k], cb, sk, alive, cid, ckey, ev, pe, rcheck);
+  fin_flush(A, ev, pe, rcheck);
 }
 
 // ---------------------------------------------------------------- big rows
@@ -225,6 +262,10 @@ hipError_t go(const FinalizeArgs& a, const FinalizeBig& big, hipStream_t st) {
   if (a.gram && grid > kGramSlots) grid = kGramSlots;  // one Gram scratch per block
   k_finalize<DK, L, NCH><<<grid, 64, 0, st>>>(a);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int grid2 = grid < 2048 ? grid : 2048;
+  k_finalize_mid<DK, L, NCH><<<grid2, 64, 0, st>>>(a);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   uint32_t nbig = 0;
   e = hipMemcpyAsync(&nbig, a.nbig, 4, hipMemcpyDeviceToHost, st);

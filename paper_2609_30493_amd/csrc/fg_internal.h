@@ -115,6 +115,8 @@ struct FinalizeArgs {
   int* status;
   uint32_t* big;   // points whose candidates exceed the on-chip bound
   uint32_t* nbig;  // their count (device, zero on entry)
+  uint32_t* mid;   // points for the second on-chip tier
+  uint32_t* nmid;  // their count (device, zero on entry)
   int d;
   float* gram;     // float32 rows longer than 256 elements: Gram scratch per block (or NULL)
 };

@@ -31,6 +31,8 @@ DATASETS = {
     # thousands of entries in S0, in the merges and in finalize
     "hub-u8-6000": lambda: (gen.hub_u8(6000, 128, 1), "l2"),
     "hub-f32-6000": lambda: (gen.hub_f32(6000, 32, 2), "l2"),
+    # a hub with ~1500 finalize candidates: finalize's second on-chip tier
+    "hub-f32-1500": lambda: (gen.hub_f32(1500, 32, 3), "l2"),
 }
 
 
@@ -145,6 +147,7 @@ BUILDS = [
     ("pair-2", 2, 4, 4, 1.2, 1),
     ("hub-u8-6000", 4, 32, 16, 1.2, 2),
     ("hub-f32-6000", 4, 32, 16, 1.2, 3),
+    ("hub-f32-1500", 4, 32, 16, 1.2, 2),
 ]
 
 
