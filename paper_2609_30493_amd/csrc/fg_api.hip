@@ -296,8 +296,9 @@ fg_status merge_rows_all(int64_t n, const uint64_t* off0, const uint32_t* ids0, 
                          hipStream_t st, bool device_only = false) {
   Ctl* ctl = reinterpret_cast<Ctl*>(at(ws, m.ctl));
   uint32_t* big = reinterpret_cast<uint32_t*>(at(ws, m.big));
-  FG_HIP(fill_u32(&ctl->nbig, 0, 1, st));
-  FG_HIP(merge_rows(n, off0, ids0, aoff, addbuf, tmp, newlen, big, &ctl->nbig, st));
+  FG_HIP(fill_u32(&ctl->nbig, 0, 2, st));  // nbig and nmid
+  FG_HIP(merge_rows(n, off0, ids0, aoff, addbuf, tmp, newlen, big, &ctl->nbig,
+                    reinterpret_cast<uint32_t*>(at(ws, m.mid)), &ctl->nmid, st));
   if (device_only) {
     FG_HIP(merge_big_rows_dev(big, &ctl->nbig, off0, ids0, aoff, addbuf,
                               reinterpret_cast<uint32_t*>(at(ws, m.keys2)), tmp, newlen, st));

@@ -138,22 +138,77 @@ __global__ void k_edges_scatter(int64_t n, const uint32_t* rows, const uint32_t*
 // One wave per row v: the old row (sorted, unique) united with the row's
 // additions (any order, repeats allowed) -> sorted unique, written at the
 // row's upper-bound slot off[v] + addoff[v] of tmp; its length to newlen[v].
+// Two on-chip tiers: rows with at most kMergeSmall additions first (small
+// LDS, many waves per compute unit); rows up to kMergeAddMax are listed for
+// the second tier; rows beyond that for the big-row paths.
 constexpr int kMergeAddMax = 2048;
+constexpr int kMergeSmall = 256;
+
+template <int CAP>
+__device__ void merge_row(int64_t v, const uint64_t* off, const uint32_t* ids, const uint64_t* addoff,
+                          const uint32_t* addbuf, uint32_t* tmp, uint32_t* newlen, uint32_t* buf, uint32_t* uni) {
+  const int lane = lane_id();
+  const uint64_t o0 = off[v];
+  const int64_t o = (int64_t)(off[v + 1] - o0);
+  const uint64_t a0 = addoff[v];
+  const int64_t a = (int64_t)(addoff[v + 1] - a0);
+  uint32_t* dst = tmp + o0 + a0;
+  int M = 64;
+  while (M < a) M <<= 1;
+  for (int i = lane; i < M; i += 64) buf[i] = i < a ? addbuf[a0 + i] : FG_NONE;
+  wave_sync();
+  wave_sort_lds<uint32_t>(buf, M);
+  // keep first occurrences that are not already in the old row
+  int u = 0;
+  for (int base = 0; base < M; base += 64) {
+    int i = base + lane;
+    uint32_t x = buf[i];
+    bool keep = x != FG_NONE && (i == 0 || buf[i - 1] != x);
+    if (keep) {
+      int lo = 0, hi = (int)o;
+      while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (ids[o0 + mid] < x) lo = mid + 1;
+        else hi = mid;
+      }
+      keep = !(lo < o && ids[o0 + lo] == x);
+    }
+    uint64_t m = ballot(keep);
+    if (keep) uni[u + popc64(m & lanes_below())] = x;
+    u += popc64(m);
+  }
+  wave_sync();
+  for (int64_t j = lane; j < o; j += 64) {
+    uint32_t x = ids[o0 + j];
+    dst[j + lower_bound_lds<uint32_t>(uni, u, x)] = x;
+  }
+  for (int i = lane; i < u; i += 64) {
+    uint32_t x = uni[i];
+    int lo = 0, hi = (int)o;
+    while (lo < hi) {
+      int mid = (lo + hi) >> 1;
+      if (ids[o0 + mid] < x) lo = mid + 1;
+      else hi = mid;
+    }
+    dst[i + lo] = x;
+  }
+  if (lane == 0) newlen[v] = (uint32_t)(o + u);
+  wave_sync();
+}
 
 __global__ void __launch_bounds__(64) k_merge_rows(int64_t n, const uint64_t* off, const uint32_t* ids,
                                                    const uint64_t* addoff, const uint32_t* addbuf,
                                                    uint32_t* tmp, uint32_t* newlen, uint32_t* big,
-                                                   uint32_t* nbig) {
-  __shared__ uint32_t buf[kMergeAddMax];
-  __shared__ uint32_t uni[kMergeAddMax];
+                                                   uint32_t* nbig, uint32_t* mid, uint32_t* nmid) {
+  __shared__ uint32_t buf[kMergeSmall];
+  __shared__ uint32_t uni[kMergeSmall];
   const int lane = lane_id();
   for (int64_t v = blockIdx.x; v < n; v += gridDim.x) {
     const uint64_t o0 = off[v];
     const int64_t o = (int64_t)(off[v + 1] - o0);
-    const uint64_t a0 = addoff[v];
-    const int64_t a = (int64_t)(addoff[v + 1] - a0);
-    uint32_t* dst = tmp + o0 + a0;
+    const int64_t a = (int64_t)(addoff[v + 1] - addoff[v]);
     if (a == 0) {
+      uint32_t* dst = tmp + o0 + addoff[v];
       for (int64_t j = lane; j < o; j += 64) dst[j] = ids[o0 + j];
       if (lane == 0) newlen[v] = (uint32_t)o;
       continue;
@@ -166,48 +221,23 @@ __global__ void __launch_bounds__(64) k_merge_rows(int64_t n, const uint64_t* of
       }
       continue;
     }
-    int M = 64;
-    while (M < a) M <<= 1;
-    for (int i = lane; i < M; i += 64) buf[i] = i < a ? addbuf[a0 + i] : FG_NONE;
-    wave_sync();
-    wave_sort_lds<uint32_t>(buf, M);
-    // keep first occurrences that are not already in the old row
-    int u = 0;
-    for (int base = 0; base < M; base += 64) {
-      int i = base + lane;
-      uint32_t x = buf[i];
-      bool keep = x != FG_NONE && (i == 0 || buf[i - 1] != x);
-      if (keep) {
-        int lo = 0, hi = (int)o;
-        while (lo < hi) {
-          int mid = (lo + hi) >> 1;
-          if (ids[o0 + mid] < x) lo = mid + 1;
-          else hi = mid;
-        }
-        keep = !(lo < o && ids[o0 + lo] == x);
-      }
-      uint64_t m = ballot(keep);
-      if (keep) uni[u + popc64(m & lanes_below())] = x;
-      u += popc64(m);
+    if (a > kMergeSmall) {  // handled by the second tier
+      if (lane == 0) mid[atomicAdd(nmid, 1u)] = (uint32_t)v;
+      continue;
     }
-    wave_sync();
-    for (int64_t j = lane; j < o; j += 64) {
-      uint32_t x = ids[o0 + j];
-      dst[j + lower_bound_lds<uint32_t>(uni, u, x)] = x;
-    }
-    for (int i = lane; i < u; i += 64) {
-      uint32_t x = uni[i];
-      int lo = 0, hi = (int)o;
-      while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (ids[o0 + mid] < x) lo = mid + 1;
-        else hi = mid;
-      }
-      dst[i + lo] = x;
-    }
-    if (lane == 0) newlen[v] = (uint32_t)(o + u);
-    wave_sync();
+    merge_row<kMergeSmall>(v, off, ids, addoff, addbuf, tmp, newlen, buf, uni);
   }
+}
+
+__global__ void __launch_bounds__(64) k_merge_rows_mid(const uint64_t* off, const uint32_t* ids,
+                                                       const uint64_t* addoff, const uint32_t* addbuf,
+                                                       uint32_t* tmp, uint32_t* newlen, const uint32_t* mid,
+                                                       const uint32_t* nmid) {
+  __shared__ uint32_t buf[kMergeAddMax];
+  __shared__ uint32_t uni[kMergeAddMax];
+  const uint32_t nm = *nmid;
+  for (uint32_t k = blockIdx.x; k < nm; k += gridDim.x)
+    merge_row<kMergeAddMax>(mid[k], off, ids, addoff, addbuf, tmp, newlen, buf, uni);
 }
 
 // Rows with more than kMergeAddMax additions without the host: workgroups of
@@ -581,9 +611,12 @@ hipError_t merge_big_rows_dev(const uint32_t* big, const uint32_t* nbig, const u
 
 hipError_t merge_rows(int64_t n, const uint64_t* off, const uint32_t* ids, const uint64_t* addoff,
                       const uint32_t* addbuf, uint32_t* tmp, uint32_t* newlen, uint32_t* big, uint32_t* nbig,
-                      hipStream_t st) {
+                      uint32_t* mid, uint32_t* nmid, hipStream_t st) {
   int grid = (int)(n < 65536 ? n : 65536);
-  k_merge_rows<<<grid, 64, 0, st>>>(n, off, ids, addoff, addbuf, tmp, newlen, big, nbig);
+  k_merge_rows<<<grid, 64, 0, st>>>(n, off, ids, addoff, addbuf, tmp, newlen, big, nbig, mid, nmid);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_merge_rows_mid<<<grid < 2048 ? grid : 2048, 64, 0, st>>>(off, ids, addoff, addbuf, tmp, newlen, mid, nmid);
   return hipGetLastError();
 }
 

@@ -73,7 +73,7 @@ hipError_t edges_scatter(int64_t n, const uint32_t* rows, const uint32_t* cnt, i
 // holds 2 * additions entries).
 hipError_t merge_rows(int64_t n, const uint64_t* off, const uint32_t* ids, const uint64_t* addoff,
                       const uint32_t* addbuf, uint32_t* tmp, uint32_t* newlen, uint32_t* big, uint32_t* nbig,
-                      hipStream_t st);
+                      uint32_t* mid, uint32_t* nmid, hipStream_t st);
 struct KSeg {
   uint64_t start;
   uint32_t len, pad;
