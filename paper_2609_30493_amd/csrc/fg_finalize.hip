@@ -185,7 +185,8 @@ __global__ void __launch_bounds__(64) k_fin_big_keys(FinalizeArgs A, const KSeg*
 }
 
 template <int DK, int L, int NCH>
-__global__ void __launch_bounds__(64) k_fin_big_prune(FinalizeArgs A, const KSeg* segs, const uint64_t* keys) {
+__global__ void __launch_bounds__(64) k_fin_big_prune(FinalizeArgs A, const KSeg* segs, const uint64_t* keys,
+                                                      uint32_t* segs_tail) {
   __shared__ uint32_t kept[kFinKeptMax];
   __shared__ uint64_t sk[64];
   __shared__ uint32_t alive[2];
@@ -198,6 +199,7 @@ __global__ void __launch_bounds__(64) k_fin_big_prune(FinalizeArgs A, const KSeg
   unsigned long long ev = 0, pe = 0;
   int kc = 0;
   bool full = false;
+  uint32_t tail = sg.len;
   uint64_t carry = FG_KEY_NONE;
   for (uint32_t base = 0; base < sg.len; base += 64) {
     uint32_t j = base + lane;
@@ -233,7 +235,6 @@ __global__ void __launch_bounds__(64) k_fin_big_prune(FinalizeArgs A, const KSeg
       }
       wave_sync();
     }
-    if (full) continue;
     // resolve the chunk's survivors among themselves
     uint64_t lm = ballot(live);
     int nl = popc64(lm);
@@ -246,13 +247,73 @@ __global__ void __launch_bounds__(64) k_fin_big_prune(FinalizeArgs A, const KSeg
     }
     wave_sync();
     (void)myslot;
+    if (full) {  // the rest only counts tests against the first R-1 kept rows
+      tail = base + 64;
+      break;
+    }
   }
   uint32_t* out = A.g_nbrs + (uint64_t)p * R;
   for (int t = lane; t < R; t += 64) out[t] = t < kc ? kept[t] : FG_NONE;
   if (lane == 0) {
     A.g_cnt[p] = (uint32_t)kc;
+    segs_tail[blockIdx.x] = tail;
     atomicAdd(&A.counters[0], ev);
     atomicAdd(&A.counters[1], pe);
+  }
+}
+
+// The candidates after the chunk in which the R-th row was kept, spread
+// over kTailBlocks workgroups per big row: each unique candidate is tested
+// against kept rows 0..R-2 in order until one occludes it.  The tests and
+// the candidates only feed the counters; the row is already final.
+constexpr int kTailBlocks = 32;
+
+template <int DK, int L, int NCH>
+__global__ void __launch_bounds__(64) k_fin_big_tail(FinalizeArgs A, const KSeg* segs, const uint32_t* segs_tail,
+                                                     const uint64_t* keys) {
+  __shared__ uint32_t kept[kFinKeptMax];
+  __shared__ uint32_t cid[64];
+  __shared__ uint64_t ckey[64];
+  const int lane = lane_id(), g = lane % L;
+  const uint32_t r = blockIdx.x / kTailBlocks, q = blockIdx.x % kTailBlocks;
+  const uint32_t p = A.big[r];
+  const KSeg sg = segs[r];
+  const uint32_t tail = segs_tail[r];
+  const int R = A.R;
+  if (tail >= sg.len) return;
+  for (int t = lane; t < R - 1; t += 64) kept[t] = A.g_nbrs[(uint64_t)p * R + t];
+  wave_sync();
+  unsigned long long ev = 0, pe = 0;
+  for (uint32_t base = tail + 64 * q; base < sg.len; base += 64 * kTailBlocks) {
+    uint32_t j = base + lane;
+    uint64_t x = j < sg.len ? keys[sg.start + j] : FG_KEY_NONE;
+    uint64_t prev = shfl64(x, lane > 0 ? lane - 1 : 0);
+    if (lane == 0) prev = base > 0 ? keys[sg.start + base - 1] : FG_KEY_NONE;
+    bool live = x != FG_KEY_NONE && x != prev;
+    ev += (unsigned long long)popc64(ballot(live));
+    for (int i = 0; i < R - 1; i++) {
+      uint64_t lm = ballot(live);
+      int nl = popc64(lm);
+      if (nl == 0) break;
+      if (live) cid[popc64(lm & lanes_below())] = key_id(x);
+      wave_sync();
+      Chunks<L, NCH> kcn;
+      load_chunks<L, NCH>(kcn, A.X.x + (size_t)kept[i] * A.X.stride, A.X.Q, g);
+      uint32_t kn = 0;
+      if constexpr (DK == U8L2) kn = group_sum_u32<L>(u8_selfdot<L, NCH>(kcn));
+      batch_dists_rs<DK, L, NCH>(A.X, kcn, kn, cid, nl, ckey);
+      pe += (unsigned long long)nl;
+      if (live) {
+        float dkc = hi_to_float<DK>(key_hi(ckey[popc64(lm & lanes_below())]));
+        float dpc = hi_to_float<DK>(key_hi(x));
+        if (A.alpha * dkc <= dpc) live = false;
+      }
+      wave_sync();
+    }
+  }
+  if (lane == 0) {
+    if (ev) atomicAdd(&A.counters[0], ev);
+    if (pe) atomicAdd(&A.counters[1], pe);
   }
 }
 
@@ -281,7 +342,11 @@ hipError_t go(const FinalizeArgs& a, const FinalizeBig& big, hipStream_t st) {
   k_fin_big_keys<DK, L, NCH><<<nbig, 64, 0, st>>>(a, big.segs, big.keys);
   e = segsort_u64(big.keys, big.keys2, big.segs, hsegs, big.tiles, big.tile_cap, st);
   if (e != hipSuccess) return e;
-  k_fin_big_prune<DK, L, NCH><<<nbig, 64, 0, st>>>(a, big.segs, big.keys);
+  uint32_t* tails = reinterpret_cast<uint32_t*>(big.keys2);  // free after the sort
+  k_fin_big_prune<DK, L, NCH><<<nbig, 64, 0, st>>>(a, big.segs, big.keys, tails);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_fin_big_tail<DK, L, NCH><<<nbig * kTailBlocks, 64, 0, st>>>(a, big.segs, tails, big.keys);
   return hipGetLastError();
 }
 
