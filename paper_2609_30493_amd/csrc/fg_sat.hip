@@ -450,19 +450,25 @@ __global__ void __launch_bounds__(64) k_sat_copy_back(SatArgs A) {
 // ---------------------------------------------------------------- small bags
 // One wave builds the whole subtree of a small bag.  The stack lives in the
 // bag's own range of the stack arrays (a subtree has at most len nodes).
-template <int DK, int L, int NCH>
+constexpr int kSmallLo = 256;
+
+template <int DK, int L, int NCH, int CAP>
 __global__ void __launch_bounds__(64) k_sat_small(SatArgs A, uint32_t nsmall) {
-  __shared__ uint64_t sk[kSmall];
-  __shared__ uint32_t nb[kSmall];
-  __shared__ uint32_t own[kSmall];
-  __shared__ uint32_t cc[kSmall];
-  __shared__ uint32_t alive[kSmall / 32];
+  // bags of at most kSmallLo points take the instance with the small LDS
+  // footprint (more waves per compute unit), larger ones the other
+  constexpr bool kLo = CAP <= kSmallLo;
+  __shared__ uint64_t sk[CAP];
+  __shared__ uint32_t nb[CAP];
+  __shared__ uint32_t own[CAP];
+  __shared__ uint32_t cc[CAP];
+  __shared__ uint32_t alive[CAP / 32];
   __shared__ uint32_t cid[64];
   __shared__ uint64_t ckey[64];
   const int lane = lane_id(), g = lane % L;
   unsigned long long ev_keys = 0, ev_acc = 0, ev_asg = 0;
   for (uint32_t si = blockIdx.x; si < nsmall; si += gridDim.x) {
     const SatSeg sg = A.small[si];
+    if ((sg.len <= (uint32_t)kSmallLo) != kLo) continue;
     uint32_t* sa = A.stk_a + sg.start;
     uint32_t* ss = A.stk_s + sg.start;
     uint32_t* sm = A.stk_m + sg.start;
@@ -611,17 +617,18 @@ struct SatKernels {
   static void* resolve() { return (void*)&k_sat_resolve<DK, L, NCH>; }
   static void* filter() { return (void*)&k_sat_filter<DK, L, NCH>; }
   static void* assign() { return (void*)&k_sat_assign<DK, L, NCH>; }
-  static void* small() { return (void*)&k_sat_small<DK, L, NCH>; }
+  static void* small_lo() { return (void*)&k_sat_small<DK, L, NCH, kSmallLo>; }
+  static void* small() { return (void*)&k_sat_small<DK, L, NCH, kSmall>; }
 };
 
 struct KSet {
-  void *keys, *resolve, *filter, *assign, *small;
+  void *keys, *resolve, *filter, *assign, *small_lo, *small;
 };
 
 template <int DK, int L, int NCH>
 KSet kset() {
   using K = SatKernels<DK, L, NCH>;
-  return KSet{K::keys(), K::resolve(), K::filter(), K::assign(), K::small()};
+  return KSet{K::keys(), K::resolve(), K::filter(), K::assign(), K::small_lo(), K::small()};
 }
 
 bool pick_kset(int dk, int Q, KSet* k) {
@@ -846,6 +853,7 @@ hipError_t sat_build_multi(const Shape& s, uint32_t T, const std::vector<SatInst
   if (nsmall) {
     unsigned grid = nsmall < 65536 ? nsmall : 65536;
     void* args[] = {&a, &nsmall};
+    CK(hipLaunchKernel(K.small_lo, dim3(grid), dim3(64), args, 0, st));
     CK(hipLaunchKernel(K.small, dim3(grid), dim3(64), args, 0, st));
   }
   unsigned long long ev[3];
