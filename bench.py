@@ -194,8 +194,9 @@ def hodges_lehmann(logr: np.ndarray) -> float:
 
 def screen_compare(args):
     """Mixed precision against float32 (paired protocol): whole builds of
-    the same workload plain, bf16-screened and fp8-screened, in a seeded
-    random order within each repetition; the graph hash must be identical
+    the same workload plain, bf16-screened, fp8-screened and (d > 256)
+    with the bf16-split prune tiles alone, in a seeded random order within
+    each repetition; the graph hash must be identical
     on every run.  Ratio = plain time / screened time; Hodges-Lehmann
     estimate over repetitions and the exact Wilcoxon signed-rank p."""
     from scipy import stats
@@ -210,8 +211,10 @@ def screen_compare(args):
         metric = "cosine" if w.metric == "cosine" else "l2"
         data = F.make_data(xd, metric)
         forms = (F.SCREEN_NONE, F.SCREEN_BF16, F.SCREEN_FP8E4M3)
+        if w.d > 256:
+            forms += (F.SCREEN_BF16_PRUNE,)
         params = {f: F.make_params(w.T, w.ef_h, w.R, w.alpha, w.B, screen=f) for f in forms}
-        ws = F.alloc_workspace(data, params[F.SCREEN_BF16])  # the largest of the three layouts
+        ws = F.alloc_workspace(data, params[F.SCREEN_BF16])  # the largest of the layouts
         G = F.make_graph(*(torch.full(sh, -1, dtype=torch.int32, device="cuda")
                            for sh in ((n, w.R), (n,), (n,), (w.T,))), w.T)
         hashes = {}
@@ -232,24 +235,27 @@ def screen_compare(args):
                 wall = time.perf_counter() - t0
                 assert F.graph_hash(G) == hashes[F.SCREEN_NONE]
                 res[f].append(dict(harvest_ms=t["harvest_ms"], build_s=wall, screen_ms=t["screen_ms"],
-                                   evals=c["harvest_evals"], rejected=c["screen_rejected"]))
+                                   finalize_ms=t["finalize_ms"], evals=c["harvest_evals"],
+                                   rejected=c["screen_rejected"], rechecks=c["prune_rechecks"]))
                 log(f"[screen] rep {rep} form {f}: harvest {t['harvest_ms']:.0f} ms build {wall:.2f} s")
         row = {"workload": w.name, "n": n, "d": w.d, "metric": metric, "graph_hash": f"{hashes[0]:#018x}",
                "harvest_evals": res[0][0]["evals"], "forms": {}}
         base_h = np.array([r["harvest_ms"] for r in res[0]])
         base_b = np.array([r["build_s"] for r in res[0]])
         row_bytes = 4 * w.d
-        for f, name in zip(forms, ("fp32", "bf16", "fp8e4m3")):
+        for f, name in zip(forms, ("fp32", "bf16", "fp8e4m3", "bf16split_prune")):
             h = np.array([r["harvest_ms"] for r in res[f]])
             b = np.array([r["build_s"] for r in res[f]])
             ev = res[f][0]["evals"]
             rej = res[f][0]["rejected"]
-            narrow = {0: 0, 1: 2 * w.d, 2: w.d}[f]
+            narrow = {0: 0, 1: 2 * w.d, 2: w.d, 3: 0}[f]
             e = {"harvest_ms_median": float(np.median(h)), "build_s_median": float(np.median(b)),
                  "harvest_evals_per_s": float(ev / (np.median(h) / 1e3)),
                  "screen_rejected_frac": rej / ev,
                  "bytes_per_eval": narrow + (1 - rej / ev) * row_bytes if f else row_bytes,
-                 "screen_copy_ms": float(np.median([r["screen_ms"] for r in res[f]]))}
+                 "screen_copy_ms": float(np.median([r["screen_ms"] for r in res[f]])),
+                 "finalize_ms_median": float(np.median([r["finalize_ms"] for r in res[f]])),
+                 "prune_rechecks": int(res[f][0]["rechecks"])}
             if f:
                 lr_h, lr_b = np.log(base_h / h), np.log(base_b / b)
                 e["harvest_speedup_hl"] = hodges_lehmann(lr_h)

@@ -57,17 +57,24 @@ typedef enum {
 typedef enum { FG_F32 = 0, FG_U8 = 1 } fg_dtype;
 typedef enum { FG_L2SQ = 0, FG_COSINE = 1 } fg_metric;
 
-/* Screened harvest (Sec. 5.3: an adaptive evaluation costs the bytes of one
- * row).  FG_F32 data with d > 64 only.  A narrow copy of the rows (made in
- * the workspace by the harvest entry points) gives every new candidate a
- * cheap distance and a proven error margin; a candidate that provably cannot
- * enter the full beam is not evaluated exactly.  Every other decision uses
- * the exact float32 distance, so graphs, counts and hashes are those of
- * FG_SCREEN_NONE. */
+/* Mixed-precision forms (Sec. 5.3: an adaptive evaluation costs the bytes
+ * of one row).  FG_F32 data with d > 64 only.  A narrow copy of the rows
+ * (made in the workspace by the harvest entry points) gives cheap values with
+ * proven error margins; a decision the margin settles is taken from the
+ * cheap value, every other one from the exact float32 distance, so graphs,
+ * counts and hashes are those of FG_SCREEN_NONE.
+ *   search screen (FG_SCREEN_BF16, FG_SCREEN_FP8E4M3): a new candidate that
+ *     provably cannot enter the full beam is not evaluated exactly;
+ *   split prune tiles (FG_SCREEN_BF16, FG_SCREEN_BF16_PRUNE; 256 < d <= 1024):
+ *     the occlusion prune's Gram tiles (harvest and finalize) come from a
+ *     bfloat16 split x = hi + lo + e, |e| <= 2^-16 |x| elementwise, three
+ *     bfloat16 matrix-core products per 16 elements instead of eight float32
+ *     ones. */
 typedef enum {
   FG_SCREEN_NONE = 0,
-  FG_SCREEN_BF16 = 1,     /* bfloat16 copy, round to nearest even, 2d bytes/row */
-  FG_SCREEN_FP8E4M3 = 2   /* fp8 e4m3 (OCP) copy with a power-of-two scale per row, d bytes/row */
+  FG_SCREEN_BF16 = 1,       /* bfloat16 copy, round to nearest even: search screen and split prune tiles */
+  FG_SCREEN_FP8E4M3 = 2,    /* fp8 e4m3 (OCP) copy with a power-of-two scale per row: search screen */
+  FG_SCREEN_BF16_PRUNE = 3  /* split prune tiles only (256 < d <= 1024) */
 } fg_screen;
 
 /* Row-major data in device memory.  FG_F32 needs d % 4 == 0; FG_U8 needs
@@ -276,7 +283,8 @@ fg_status fg_leaf_knn(const fg_data* data, uint32_t leaf_size, uint32_t R,
  * row i of the data as bfloat16 (round to nearest even) or as fp8 e4m3 (OCP)
  * codes of x * 2^k, k the largest integer with max|x_i| * 2^k <= 448, in
  * the data's element order, rows fg_screen_row_bytes(d, screen) bytes apart
- * (2d or d rounded up to a multiple of 16; pad bytes are not written).
+ * (bfloat16: 2d rounded up to a multiple of 32, pad bytes written as zero;
+ * fp8: d rounded up to a multiple of 16, pad bytes not written).
  * err_dev[i] >= |x^_i - x_i| and norm_dev[i] >= |x_i| (float64 sums rounded
  * up), sinv_dev[i] = 2^-k (1 for bfloat16), where x^_i is the copy read
  * back (fp8: code * 2^-k).  FG_F32 data with d > 64 only.  Asynchronous on

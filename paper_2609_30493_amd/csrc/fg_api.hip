@@ -63,17 +63,31 @@ bool check_params(const fg_params* p, int64_t n, bool need_ef = true) {
   if (p->beam_table_slots != 0 && p->beam_table_slots != 1024 && p->beam_table_slots != 2048 &&
       p->beam_table_slots != 4096)
     return set_error("beam_table_slots must be 0, 1024, 2048 or 4096"), false;
-  if (p->screen > FG_SCREEN_FP8E4M3) return set_error("screen must be an fg_screen"), false;
+  if (p->screen > FG_SCREEN_BF16_PRUNE) return set_error("screen must be an fg_screen"), false;
   if (p->waves_per_cu > 64) return set_error("waves_per_cu must be 0..64"), false;
   return true;
 }
 
-// The screened kernels exist for float32 rows of 17..256 chunks.
+// The screened kernels exist for float32 rows of 17..256 chunks, the split
+// Gram tiles for 65..256 chunks.
 bool check_screen(const fg_params* p, const Shape& s) {
   if (p->screen == FG_SCREEN_NONE) return true;
   if (s.dk == U8L2) return set_error("screening applies to FG_F32 data only"), false;
   if (s.Q <= 16 || s.Q > 256) return set_error("screening needs 64 < d <= 1024"), false;
+  if (p->screen == FG_SCREEN_BF16_PRUNE && s.Q <= 64)
+    return set_error("FG_SCREEN_BF16_PRUNE needs 256 < d <= 1024"), false;
   return true;
+}
+
+// The narrow copy's kind, and whether the prune's Gram tiles come from the
+// bfloat16 split (float32 rows of 257..1024 elements).
+int copy_kind(uint32_t screen) { return screen == FG_SCREEN_FP8E4M3 ? SCR_FP8 : SCR_BF16; }
+bool split_tiles(uint32_t screen, int d) {
+  return (screen == FG_SCREEN_BF16 || screen == FG_SCREEN_BF16_PRUNE) && d > 256 && d <= 1024 && d % 4 == 0;
+}
+// The search-side screen's kernel variant (none for FG_SCREEN_BF16_PRUNE).
+int search_screen(uint32_t screen) {
+  return screen == FG_SCREEN_BF16 ? SCR_BF16 : screen == FG_SCREEN_FP8E4M3 ? SCR_FP8 : SCR_NONE;
 }
 
 uint32_t b_eff(const fg_params* p) { return p->B > 1 ? p->B : 1; }
@@ -98,6 +112,7 @@ struct WsMap {
   size_t off[2], ids[2], rows, cnt, tparent, roots;  // the whole build
   size_t sat;
   size_t xs, xs_err, xs_norm, xs_sinv;      // screened harvest (last: only they depend on d)
+  size_t xs_lo;                             // the bfloat16 split's low plane
   size_t gram;                              // Gram-tile prune scratch (float32, d > 256)
   int64_t xs_stride;
   SatWs satw;
@@ -157,8 +172,9 @@ WsMap ws_map(int64_t n, const fg_params* p, int d = 0) {
   m.sat = take(m.satw.total);
   if (p && d > 256 && d % 4 == 0 && d <= 1024) m.gram = take((size_t)kGramSlots * kGramMax * kGramMax * 4);
   if (p && p->screen && d > 0) {
-    m.xs_stride = screen_stride(d, (int)p->screen);
+    m.xs_stride = screen_stride(d, copy_kind(p->screen));
     m.xs = take(un * (uint64_t)m.xs_stride);
+    if (split_tiles(p->screen, d)) m.xs_lo = take(un * (uint64_t)m.xs_stride);
     m.xs_err = take(un * 4);
     m.xs_norm = take(un * 4);
     m.xs_sinv = take(un * 4);
@@ -217,7 +233,7 @@ fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* id
   if (nitems == 0) return FG_OK;
   const int ef = bi ? bi->ef_max : (int)P->ef_h;
   const int hslots = beam_table_slots(ef, false, table_request(P), beam_chunks_per_lane(s));
-  const int screen = (int)P->screen;
+  const int screen = search_screen(P->screen);
   int grid = beam_grid(s, ef, false, hslots, screen, (int)P->waves_per_cu);
   if (grid <= 0) return set_error("no beam kernel for this row size / ef_h"), FG_EUNSUPPORTED;
   BeamArgs a{};
@@ -250,6 +266,7 @@ fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* id
   if (m.gram && s.dk != U8L2 && s.Q > 64) {
     a.gram = reinterpret_cast<float*>(at(ws, m.gram));
     grid = grid < kGramSlots ? grid : kGramSlots;
+    if (m.xs_lo) a.split = GramSplit{reinterpret_cast<const uint8_t*>(at(ws, m.xs)), reinterpret_cast<const uint8_t*>(at(ws, m.xs_lo)), m.xs_stride};
   }
   if (bi) {
     a.inst_of = bi->inst_of;
@@ -269,9 +286,10 @@ fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* id
 
 fg_status screen_launch(const Shape& s, const fg_params* P, void* ws, const WsMap& m, hipStream_t st) {
   if (!P->screen) return FG_OK;
-  FG_HIP(make_screen(s, (int)P->screen, reinterpret_cast<uint8_t*>(at(ws, m.xs)),
+  FG_HIP(make_screen(s, copy_kind(P->screen), reinterpret_cast<uint8_t*>(at(ws, m.xs)),
                      reinterpret_cast<float*>(at(ws, m.xs_err)), reinterpret_cast<float*>(at(ws, m.xs_norm)),
-                     reinterpret_cast<float*>(at(ws, m.xs_sinv)), st));
+                     reinterpret_cast<float*>(at(ws, m.xs_sinv)), st,
+                     m.xs_lo ? reinterpret_cast<uint8_t*>(at(ws, m.xs_lo)) : nullptr));
   return FG_OK;
 }
 
@@ -395,6 +413,7 @@ fg_status finalize_launch(const Shape& s, const uint32_t* rows, const uint32_t* 
   f.counters = ctl->fin;
   f.d = s.d;
   f.gram = (m.gram && s.dk != U8L2 && s.Q > 64) ? reinterpret_cast<float*>(at(ws, m.gram)) : nullptr;
+  if (f.gram && m.xs_lo) f.split = GramSplit{reinterpret_cast<const uint8_t*>(at(ws, m.xs)), reinterpret_cast<const uint8_t*>(at(ws, m.xs_lo)), m.xs_stride};
   f.status = &ctl->status;
   f.big = reinterpret_cast<uint32_t*>(at(ws, m.big));
   f.nbig = &ctl->nbig;

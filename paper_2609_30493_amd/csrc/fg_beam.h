@@ -63,6 +63,16 @@ static __device__ unsigned long long fg_prof_cycles[16];
   } while (0)
 #endif
 
+// Rows x = hi + lo + e in bfloat16 (hi = x rounded to nearest even, lo = the
+// remainder x - hi so rounded; |e| <= 2^-16 |x| elementwise), two planes of
+// `stride` bytes per row, zero-padded to whole 16-element steps.  hi == NULL:
+// the Gram tiles read the float32 rows.
+struct GramSplit {
+  const uint8_t* hi;
+  const uint8_t* lo;
+  int64_t stride;
+};
+
 struct BeamArgs {
   // data
   const uint8_t* x;
@@ -119,9 +129,12 @@ struct BeamArgs {
   // float32 rows of more than 64 chunks: per wave slot a kGramMax^2 float
   // scratch for the candidates' Gram matrix (NULL: exact prune only)
   float* gram;
+  // the Gram tiles from the bfloat16 split of the rows (see GramSplit)
+  GramSplit split;
 };
 
 constexpr int kGramMax = 256;    // candidates the Gram-tile prune takes
+constexpr int kGramPF16 = 2;     // split-tile steps in flight
 constexpr int kGramSlots = 2048; // wave slots that have Gram scratch
 
 enum ScreenKind { SCR_NONE = 0, SCR_BF16 = 1, SCR_FP8 = 2 };
@@ -475,6 +488,70 @@ __device__ __forceinline__ void gram_tiles(const RowSet& X, const uint64_t* sk, 
   }
 }
 
+typedef __bf16 gram_bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void gram_mfma_split(gram_f32x16& acc, const gram_bf16x8& ah, const gram_bf16x8& al,
+                                                const gram_bf16x8& bh, const gram_bf16x8& bl) {
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+}
+
+// gram_tiles from the split planes: <a,c> ~ <ah,ch> + <ah,cl> + <al,ch>
+// (the dropped <al,cl> and the residuals e are covered by the margin).  A
+// 16-element step is one 32x32x16 product per term: lane l reads the eight
+// k-values at bytes 16 (l >> 5) of the step.  Same accumulator layout and
+// stores as gram_tiles.
+__device__ __forceinline__ void gram_tiles_split(const GramSplit& gs, const uint64_t* sk, int mc, float* G) {
+  const int lane = lane_id();
+  const int nb = (mc + 31) / 32;
+  const int K = (int)(gs.stride / 32);
+  const size_t ho = 16 * (size_t)(lane >> 5);
+  for (int I = 0; I < nb; I++) {
+    const int ra = 32 * I + (lane & 31);
+    const size_t oa = (size_t)key_id(sk[ra < mc ? ra : 0]) * gs.stride + ho;
+    for (int J = I; J < nb; J++) {
+      const int rb = 32 * J + (lane & 31);
+      const size_t ob = (size_t)key_id(sk[rb < mc ? rb : 0]) * gs.stride + ho;
+      gram_f32x16 acc;
+#pragma unroll
+      for (int e = 0; e < 16; e++) acc[e] = 0.0f;
+      gram_bf16x8 ah[kGramPF16], al[kGramPF16], bh[kGramPF16], bl[kGramPF16];
+#pragma unroll
+      for (int u = 0; u < kGramPF16; u++)
+        if (u < K) {
+          ah[u] = *reinterpret_cast<const gram_bf16x8*>(gs.hi + oa + 32 * (size_t)u);
+          al[u] = *reinterpret_cast<const gram_bf16x8*>(gs.lo + oa + 32 * (size_t)u);
+          bh[u] = *reinterpret_cast<const gram_bf16x8*>(gs.hi + ob + 32 * (size_t)u);
+          bl[u] = *reinterpret_cast<const gram_bf16x8*>(gs.lo + ob + 32 * (size_t)u);
+        }
+      int c = 0;
+      for (; c + kGramPF16 <= K; c += kGramPF16) {
+#pragma unroll
+        for (int u = 0; u < kGramPF16; u++) {
+          gram_mfma_split(acc, ah[u], al[u], bh[u], bl[u]);
+          const int nx = c + u + kGramPF16;
+          if (nx < K) {
+            ah[u] = *reinterpret_cast<const gram_bf16x8*>(gs.hi + oa + 32 * (size_t)nx);
+            al[u] = *reinterpret_cast<const gram_bf16x8*>(gs.lo + oa + 32 * (size_t)nx);
+            bh[u] = *reinterpret_cast<const gram_bf16x8*>(gs.hi + ob + 32 * (size_t)nx);
+            bl[u] = *reinterpret_cast<const gram_bf16x8*>(gs.lo + ob + 32 * (size_t)nx);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kGramPF16; u++)
+        if (c + u < K) gram_mfma_split(acc, ah[u], al[u], bh[u], bl[u]);
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        const int i = 32 * I + gram_acc_row(r, lane);
+        const int j = 32 * J + (lane & 31);
+        if (i < mc && j < mc && j >= i) G[i * kGramMax + j] = acc[r];
+      }
+    }
+  }
+}
+
 // Margin for d~ against the exact declared-order distance (standard model:
 // every elementary operation of the matrix-core sum is taken to err by up to
 // 2^-23 relative, twice the float32 unit roundoff, since its internal order
@@ -485,11 +562,18 @@ __device__ __forceinline__ void gram_tiles(const RowSet& X, const uint64_t* sk, 
 //   cosine: |G_ac - <a,c>| <= gg |a||c|, the declared order gc |a||c|, two
 //     roundings of 1 - s at most 2u (1 + |a||c|) each, |a||c| <=
 //     sqrt(G_aa G_cc) / (1 - gg).
+// From the bfloat16 split the entries are sums of 3d exact products whose
+// magnitudes add up to at most (1 + 2^-8)^2 (1 + 2^-7 (1 + 2^-8)) |a||c| <=
+// 1.016 |a||c|, and the terms left out (<al,cl> and the residuals) are at
+// most 3.01 * 2^-16 |a||c|: gg = 3.1 * 2^-16 + 1.016 gamma(3d + 4), plus an
+// absolute 2^-100 (d + 4) for operands the matrix cores may flush to zero.
 // The result is doubled.
 template <int DK>
-__device__ __forceinline__ float gram_eps(float dt, float gaa, float gcc, int d) {
+__device__ __forceinline__ float gram_eps(float dt, float gaa, float gcc, int d, bool split) {
   const float u = 5.9604645e-08f;  // 2^-24
-  const float gg = (d + 4) * (2.0f * u) / (1.0f - (d + 4) * (2.0f * u));
+  const int nk = split ? 3 * d + 4 : d + 4;
+  float gg = nk * (2.0f * u) / (1.0f - nk * (2.0f * u));
+  if (split) gg = 3.1f * 1.5258789e-05f + 1.016f * gg;
   const float gc = (d / 16 + 8) * u / (1.0f - (d / 16 + 8) * u);
   float eps;
   if constexpr (DK == F32L2) {
@@ -500,6 +584,7 @@ __device__ __forceinline__ float gram_eps(float dt, float gaa, float gcc, int d)
     const float nn = __builtin_sqrtf(fabsf(gaa) * fabsf(gcc)) / (1.0f - gg);
     eps = (gg + gc) * nn + 4.0f * u * (1.0f + nn);
   }
+  if (split) eps += (float)(d + 4) * 7.888609e-31f;  // 2^-100 (d + 4)
   return 2.0f * eps;
 }
 
@@ -548,9 +633,9 @@ __device__ __forceinline__ float group_dist_stream(const uint8_t* ra, const uint
 // matrix (gram_tiles, then a fence) where the margin allows.  G is this
 // wave's kGramMax^2 scratch; *rc counts the exact recomputations.
 template <int DK, int L, int NCH>
-__device__ int prune_gram(const RowSet& X, int d, float alpha, int R, const uint64_t* sk, int mc, const float* G,
-                          uint32_t* alive, uint32_t* cid, uint64_t* ckey, uint32_t* out, unsigned long long* pe,
-                          unsigned long long* rc) {
+__device__ int prune_gram(const RowSet& X, int d, bool split, float alpha, int R, const uint64_t* sk, int mc,
+                          const float* G, uint32_t* alive, uint32_t* cid, uint64_t* ckey, uint32_t* out,
+                          unsigned long long* pe, unsigned long long* rc) {
   const int lane = lane_id();
   const int g = lane % L;
   for (int w = lane; w < (mc + 31) / 32; w += 64) {
@@ -592,7 +677,7 @@ __device__ int prune_gram(const RowSet& X, int d, float alpha, int R, const uint
         dpc = hi_to_float<DK>(key_hi(sk[j]));
         const float gcc = G[j * kGramMax + j], gac = G[i * kGramMax + j];
         const float dt = DK == F32L2 ? (gaa + gcc) - 2.0f * gac : 1.0f - gac;
-        const float eps = gram_eps<DK>(dt, gaa, gcc, d);
+        const float eps = gram_eps<DK>(dt, gaa, gcc, d, split);
         // bounds on fl(alpha * exact), widened for their own roundings
         const float up = alpha * (dt + eps), lo = alpha * (dt - eps);
         if (up + fabsf(up) * u8 < dpc) kill = true;
@@ -858,14 +943,17 @@ k_beam(BeamArgs A) {
           gram = A.gram != nullptr && mc <= kGramMax && wslot < kGramSlots;
         if (gram) {
           float* G = A.gram + (size_t)wslot * kGramMax * kGramMax;
-          gram_tiles(X, sk, mc, G);
+          if (A.split.hi)
+            gram_tiles_split(A.split, sk, mc, G);
+          else
+            gram_tiles(X, sk, mc, G);
           // the tiles were written by other lanes, and this slot's scratch
           // may sit in the vector L1 from an earlier search: make the
           // stores visible and drop stale lines before reading them back
           __threadfence();
           FG_TICK(8);
-          kept = prune_gram<DK, L, NCH>(X, A.d, A.alpha, A.R, sk, mc, G, S.alive, S.cid, S.ckey, out, &my_pe,
-                                        &my_rc);
+          kept = prune_gram<DK, L, NCH>(X, A.d, A.split.hi != nullptr, A.alpha, A.R, sk, mc, G, S.alive, S.cid,
+                                        S.ckey, out, &my_pe, &my_rc);
         } else
           kept = prune_wave<DK, L, NCH>(X, A.alpha, A.R, sk, mc, S.alive, S.cid, S.ckey, out, &my_pe);
         FG_TICK(4);

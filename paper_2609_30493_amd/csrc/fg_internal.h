@@ -47,7 +47,7 @@ void* pick_screen_fp8(int dk, int Q, int ef, int hslots);
 // bytes, and the copy with its per-row error norm, norm and fp8 factor.
 int64_t screen_stride(int d, int screen);
 hipError_t make_screen(const Shape& s, int screen, uint8_t* xs, float* err, float* norm, float* sinv,
-                       hipStream_t st);
+                       hipStream_t st, uint8_t* xs_lo = nullptr);
 
 // Small utilities (fg_graph.hip).
 hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t st);
@@ -119,6 +119,7 @@ struct FinalizeArgs {
   uint32_t* nmid;  // their count (device, zero on entry)
   int d;
   float* gram;     // float32 rows longer than 256 elements: Gram scratch per block (or NULL)
+  GramSplit split; // the Gram tiles from the bfloat16 split (hi NULL: from the rows)
 };
 struct FinalizeBig {
   KSeg* segs;

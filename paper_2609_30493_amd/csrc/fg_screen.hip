@@ -9,7 +9,9 @@
 // code * 2^-k.  For every row the norm of the actual error |u^ - u| and the
 // norm |u| are accumulated in float64 and rounded up to float32, so the
 // margin the search uses bounds the copy that the search reads, whatever
-// rounding the conversion did.
+// rounding the conversion did.  For bfloat16 an optional second plane holds
+// each element's remainder x - hi rounded to bfloat16 (lo), so that
+// hi + lo carries 16 significant bits: the prune tiles use both.
 #include "fg_internal.h"
 
 namespace fg {
@@ -45,7 +47,7 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
 template <int SCR>
 __global__ void __launch_bounds__(256) k_make_screen(const uint8_t* x, int64_t stride, int64_t n, int d,
                                                      uint8_t* xs, int64_t xs_stride, float* err, float* norm,
-                                                     float* sinv) {
+                                                     float* sinv, uint8_t* xs_lo) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -88,6 +90,15 @@ __global__ void __launch_bounds__(256) k_make_screen(const uint8_t* x, int64_t s
         w.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
         w.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
         *reinterpret_cast<uint2*>(xs + i * xs_stride + 8 * (int64_t)c) = w;
+        if (xs_lo) {  // the remainder x - hi (exact in float32), rounded to bfloat16
+          uint16_t lo[4];
+#pragma unroll
+          for (int t = 0; t < 4; t++) lo[t] = bf16_rne(a[t] - back[t]);
+          uint2 wl;
+          wl.x = (uint32_t)lo[0] | ((uint32_t)lo[1] << 16);
+          wl.y = (uint32_t)lo[2] | ((uint32_t)lo[3] << 16);
+          *reinterpret_cast<uint2*>(xs_lo + i * xs_stride + 8 * (int64_t)c) = wl;
+        }
       } else {
         int w = __builtin_amdgcn_cvt_pk_fp8_f32(a[0] * scale, a[1] * scale, 0, false);
         w = __builtin_amdgcn_cvt_pk_fp8_f32(a[2] * scale, a[3] * scale, w, true);
@@ -106,6 +117,12 @@ __global__ void __launch_bounds__(256) k_make_screen(const uint8_t* x, int64_t s
         n2 += (double)a[t] * (double)a[t];
       }
     }
+    if constexpr (SCR == SCR_BF16) {  // zero the row's padding (read by 16-element steps)
+      for (int64_t c = C + lane; c < xs_stride / 8; c += 64) {
+        *reinterpret_cast<uint2*>(xs + i * xs_stride + 8 * c) = make_uint2(0, 0);
+        if (xs_lo) *reinterpret_cast<uint2*>(xs_lo + i * xs_stride + 8 * c) = make_uint2(0, 0);
+      }
+    }
     e2 = wave_sum_f64(e2);
     n2 = wave_sum_f64(n2);
     if (lane == 0) {
@@ -120,20 +137,22 @@ __global__ void __launch_bounds__(256) k_make_screen(const uint8_t* x, int64_t s
 }  // namespace
 
 int64_t screen_stride(int d, int screen) {
-  const int64_t b = screen == SCR_BF16 ? 2 * (int64_t)d : (int64_t)d;
-  return (b + 15) / 16 * 16;
+  if (screen == SCR_BF16) return (2 * (int64_t)d + 31) / 32 * 32;  // whole 16-element steps
+  return ((int64_t)d + 15) / 16 * 16;
 }
 
 hipError_t make_screen(const Shape& s, int screen, uint8_t* xs, float* err, float* norm, float* sinv,
-                       hipStream_t st) {
+                       hipStream_t st, uint8_t* xs_lo) {
   const int64_t xst = screen_stride(s.d, screen);
   int64_t blocks = (s.n + 3) / 4;
   if (blocks > 65536) blocks = 65536;
   if (blocks < 1) blocks = 1;
   if (screen == SCR_BF16)
-    k_make_screen<SCR_BF16><<<(unsigned)blocks, 256, 0, st>>>(s.x, s.stride, s.n, s.d, xs, xst, err, norm, sinv);
+    k_make_screen<SCR_BF16><<<(unsigned)blocks, 256, 0, st>>>(s.x, s.stride, s.n, s.d, xs, xst, err, norm, sinv,
+                                                              xs_lo);
   else
-    k_make_screen<SCR_FP8><<<(unsigned)blocks, 256, 0, st>>>(s.x, s.stride, s.n, s.d, xs, xst, err, norm, sinv);
+    k_make_screen<SCR_FP8><<<(unsigned)blocks, 256, 0, st>>>(s.x, s.stride, s.n, s.d, xs, xst, err, norm, sinv,
+                                                             nullptr);
   return hipGetLastError();
 }
 

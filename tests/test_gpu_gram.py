@@ -46,3 +46,32 @@ def test_gram_prune_builds_match_oracle(fgo, case):
     assert F.graph_hash(G) == want["hash"]
     for k in ("harvest_evals", "prune_evals", "expansions", "finalize_evals", "scaffold_evals"):
         assert c[k] == want["counters"][k], k
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_split_tile_builds_match_oracle(fgo, case):
+    """FG_SCREEN_BF16_PRUNE: the same graph from the bfloat16 split tiles."""
+    from paper_2609_30493_amd import fgraft as F
+    name, mk, metric, T, ef, R, B = case
+    x = np.ascontiguousarray(mk().astype(np.float32))
+    n = x.shape[0]
+    say(f"split-tile prune {name}")
+    want = fgo.build_graph(fgo.Data(x, metric=metric), 42, fgo.params(T, ef, R, 1.2, B, 0, 8))
+    data = F.make_data(dev(x), metric)
+    out = {}
+    for scr in (F.SCREEN_NONE, F.SCREEN_BF16_PRUNE):
+        params = F.make_params(T, ef, R, 1.2, B, screen=scr)
+        ws = F.alloc_workspace(data, params)
+        gn, gcnt, sp, rt = empty_u32(n, R), empty_u32(n, fill=0), empty_u32(n), empty_u32(T)
+        G = F.make_graph(gn, gcnt, sp, rt, T)
+        c, _ = F.build_graph(data, 42, params, G, ws, timings=True)
+        assert np.array_equal(host_u32(gcnt), want["cnt"])
+        assert np.array_equal(host_u32(gn), want["nbrs"])
+        assert F.graph_hash(G) == want["hash"]
+        for k in ("harvest_evals", "prune_evals", "expansions", "finalize_evals", "scaffold_evals"):
+            assert c[k] == want["counters"][k], k
+        assert c["screen_rejected"] == 0
+        out[scr] = c["prune_rechecks"]
+    say(f"  rechecks float32 tiles {out[F.SCREEN_NONE]}, split tiles {out[F.SCREEN_BF16_PRUNE]}")
+    if not name.startswith("offset"):  # there every test cancels and is rechecked either way
+        assert out[F.SCREEN_BF16_PRUNE] <= 20 * out[F.SCREEN_NONE] + 200

@@ -174,7 +174,14 @@ def test_screen_argument_errors():
     with pytest.raises(F.FgError) as e:
         F.screen_copy(d64, F.SCREEN_BF16)
     assert e.value.code == F.FG_EUNSUPPORTED
-    p = F.make_params(4, 32, 16, 1.2, 2, screen=3)
+    x192 = dev(gen.isotropic_f32(500, 192, 4, 0.1, 2))
+    p3 = F.make_params(4, 32, 16, 1.2, 2, screen=F.SCREEN_BF16_PRUNE)
+    with pytest.raises(F.FgError) as e:  # the split tiles need 256 < d <= 1024
+        F.build_graph(F.make_data(x192), 1, p3, F.make_graph(empty_u32(500, 16), empty_u32(500), empty_u32(500),
+                                                             empty_u32(4), 4),
+                      torch.empty(1 << 26, dtype=torch.uint8, device="cuda"))
+    assert e.value.code == F.FG_EUNSUPPORTED
+    p = F.make_params(4, 32, 16, 1.2, 2, screen=4)
     with pytest.raises(F.FgError) as e:
         F.build_graph(d64, 1, p, F.make_graph(empty_u32(500, 16), empty_u32(500), empty_u32(500),
                                               empty_u32(4), 4), torch.empty(1 << 20, dtype=torch.uint8,
