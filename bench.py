@@ -213,8 +213,10 @@ def screen_compare(args):
         forms = (F.SCREEN_NONE, F.SCREEN_BF16, F.SCREEN_FP8E4M3)
         if w.d > 256:
             forms += (F.SCREEN_BF16_PRUNE,)
+        if args.forms:
+            forms = (F.SCREEN_NONE,) + tuple(int(f) for f in args.forms.split(",") if int(f) in forms[1:])
         params = {f: F.make_params(w.T, w.ef_h, w.R, w.alpha, w.B, screen=f) for f in forms}
-        ws = F.alloc_workspace(data, params[F.SCREEN_BF16])  # the largest of the layouts
+        ws = F.alloc_workspace(data, params[max(forms, key=lambda f: F.workspace_size(data, params[f]))])
         G = F.make_graph(*(torch.full(sh, -1, dtype=torch.int32, device="cuda")
                            for sh in ((n, w.R), (n,), (n,), (w.T,))), w.T)
         hashes = {}
@@ -243,7 +245,8 @@ def screen_compare(args):
         base_h = np.array([r["harvest_ms"] for r in res[0]])
         base_b = np.array([r["build_s"] for r in res[0]])
         row_bytes = 4 * w.d
-        for f, name in zip(forms, ("fp32", "bf16", "fp8e4m3", "bf16split_prune")):
+        names = {0: "fp32", 1: "bf16", 2: "fp8e4m3", 3: "bf16split_prune"}
+        for f, name in ((f, names[f]) for f in forms):
             h = np.array([r["harvest_ms"] for r in res[f]])
             b = np.array([r["build_s"] for r in res[f]])
             ev = res[f][0]["evals"]
@@ -361,6 +364,8 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="batched mode: shrink every instance's n")
     ap.add_argument("--workloads", default="cfg3,cfg4", help="screen mode: cfg3, cfg4 or both")
     ap.add_argument("--reps", type=int, default=3, help="screen mode: paired repetitions")
+    ap.add_argument("--forms", default="", help="screen mode: fg_screen values to compare with float32 "
+                                                 "(default: all that apply)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)

@@ -112,7 +112,8 @@ struct WsMap {
   size_t off[2], ids[2], rows, cnt, tparent, roots;  // the whole build
   size_t sat;
   size_t xs, xs_err, xs_norm, xs_sinv;      // screened harvest (last: only they depend on d)
-  size_t xs_lo;                             // the bfloat16 split's low plane
+  size_t xsp;                               // the bfloat16 split (interleaved hi/lo)
+  int64_t xsp_stride;
   size_t gram;                              // Gram-tile prune scratch (float32, d > 256)
   int64_t xs_stride;
   SatWs satw;
@@ -173,8 +174,11 @@ WsMap ws_map(int64_t n, const fg_params* p, int d = 0) {
   if (p && d > 256 && d % 4 == 0 && d <= 1024) m.gram = take((size_t)kGramSlots * kGramMax * kGramMax * 4);
   if (p && p->screen && d > 0) {
     m.xs_stride = screen_stride(d, copy_kind(p->screen));
-    m.xs = take(un * (uint64_t)m.xs_stride);
-    if (split_tiles(p->screen, d)) m.xs_lo = take(un * (uint64_t)m.xs_stride);
+    if (search_screen(p->screen) != SCR_NONE) m.xs = take(un * (uint64_t)m.xs_stride);
+    if (split_tiles(p->screen, d)) {
+      m.xsp_stride = split_stride(d);
+      m.xsp = take(un * (uint64_t)m.xsp_stride);
+    }
     m.xs_err = take(un * 4);
     m.xs_norm = take(un * 4);
     m.xs_sinv = take(un * 4);
@@ -266,7 +270,7 @@ fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* id
   if (m.gram && s.dk != U8L2 && s.Q > 64) {
     a.gram = reinterpret_cast<float*>(at(ws, m.gram));
     grid = grid < kGramSlots ? grid : kGramSlots;
-    if (m.xs_lo) a.split = GramSplit{reinterpret_cast<const uint8_t*>(at(ws, m.xs)), reinterpret_cast<const uint8_t*>(at(ws, m.xs_lo)), m.xs_stride};
+    if (m.xsp) a.split = GramSplit{reinterpret_cast<const uint8_t*>(at(ws, m.xsp)), m.xsp_stride};
   }
   if (bi) {
     a.inst_of = bi->inst_of;
@@ -286,10 +290,10 @@ fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* id
 
 fg_status screen_launch(const Shape& s, const fg_params* P, void* ws, const WsMap& m, hipStream_t st) {
   if (!P->screen) return FG_OK;
-  FG_HIP(make_screen(s, copy_kind(P->screen), reinterpret_cast<uint8_t*>(at(ws, m.xs)),
+  FG_HIP(make_screen(s, copy_kind(P->screen), m.xs ? reinterpret_cast<uint8_t*>(at(ws, m.xs)) : nullptr,
                      reinterpret_cast<float*>(at(ws, m.xs_err)), reinterpret_cast<float*>(at(ws, m.xs_norm)),
                      reinterpret_cast<float*>(at(ws, m.xs_sinv)), st,
-                     m.xs_lo ? reinterpret_cast<uint8_t*>(at(ws, m.xs_lo)) : nullptr));
+                     m.xsp ? reinterpret_cast<uint8_t*>(at(ws, m.xsp)) : nullptr));
   return FG_OK;
 }
 
@@ -413,7 +417,7 @@ fg_status finalize_launch(const Shape& s, const uint32_t* rows, const uint32_t* 
   f.counters = ctl->fin;
   f.d = s.d;
   f.gram = (m.gram && s.dk != U8L2 && s.Q > 64) ? reinterpret_cast<float*>(at(ws, m.gram)) : nullptr;
-  if (f.gram && m.xs_lo) f.split = GramSplit{reinterpret_cast<const uint8_t*>(at(ws, m.xs)), reinterpret_cast<const uint8_t*>(at(ws, m.xs_lo)), m.xs_stride};
+  if (f.gram && m.xsp) f.split = GramSplit{reinterpret_cast<const uint8_t*>(at(ws, m.xsp)), m.xsp_stride};
   f.status = &ctl->status;
   f.big = reinterpret_cast<uint32_t*>(at(ws, m.big));
   f.nbig = &ctl->nbig;

@@ -64,12 +64,12 @@ static __device__ unsigned long long fg_prof_cycles[16];
 #endif
 
 // Rows x = hi + lo + e in bfloat16 (hi = x rounded to nearest even, lo = the
-// remainder x - hi so rounded; |e| <= 2^-16 |x| elementwise), two planes of
-// `stride` bytes per row, zero-padded to whole 16-element steps.  hi == NULL:
-// the Gram tiles read the float32 rows.
+// remainder x - hi so rounded; |e| <= 2^-16 |x| elementwise), `stride` bytes
+// per row in 64-byte steps of 16 elements (32 bytes of hi, then 32 of lo),
+// zero-padded to whole steps.  p == NULL: the Gram tiles read the float32
+// rows.
 struct GramSplit {
-  const uint8_t* hi;
-  const uint8_t* lo;
+  const uint8_t* p;
   int64_t stride;
 };
 
@@ -134,7 +134,7 @@ struct BeamArgs {
 };
 
 constexpr int kGramMax = 256;    // candidates the Gram-tile prune takes
-constexpr int kGramPF16 = 2;     // split-tile steps in flight
+constexpr int kGramPF16 = 4;     // split-tile steps in flight
 constexpr int kGramSlots = 2048; // wave slots that have Gram scratch
 
 enum ScreenKind { SCR_NONE = 0, SCR_BF16 = 1, SCR_FP8 = 2 };
@@ -421,11 +421,12 @@ __device__ __forceinline__ int gram_acc_row(int r, int lane) { return (r >> 2) *
 
 // G[i * kGramMax + j] = <c_i, c_j> for j >= i, candidates c_i = row of sk[i].
 // Lanes l and l+32 read chunks c and c+1 of the same row: the four elements
-// of each 16-byte chunk are four k-steps of the 32x32x2 product.  Rows past
-// mc read candidate 0 (in bounds; their results are not stored), so the
-// loop has no per-lane branches and keeps kGramPF chunk pairs in flight.
-constexpr int kGramPF = 4;
-
+// of each 16-byte chunk are four k-steps of the 32x32x2 product.  Rows are
+// taken in steps of eight chunks (one 128-byte line per row), double-
+// buffered: a step's four loads per operand are issued together, one step
+// ahead of the products, so each line is used up while it is in the vector
+// L1.  Rows past mc read candidate 0 (in bounds; their results are not
+// stored), so the loop has no per-lane branches.
 __device__ __forceinline__ void gram_mfma4(gram_f32x16& acc, const float4& a, const float4& b) {
   acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, acc, 0, 0, 0);
   acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, acc, 0, 0, 0);
@@ -433,11 +434,25 @@ __device__ __forceinline__ void gram_mfma4(gram_f32x16& acc, const float4& a, co
   acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b.w, acc, 0, 0, 0);
 }
 
+__device__ __forceinline__ void gram_step_load(float4* fa, float4* fb, const uint8_t* pa, const uint8_t* pb,
+                                               int s) {
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    fa[j] = *reinterpret_cast<const float4*>(pa + 128 * (size_t)s + 32 * j);
+    fb[j] = *reinterpret_cast<const float4*>(pb + 128 * (size_t)s + 32 * j);
+  }
+}
+
+__device__ __forceinline__ void gram_step_mfma(gram_f32x16& acc, const float4* fa, const float4* fb) {
+#pragma unroll
+  for (int j = 0; j < 4; j++) gram_mfma4(acc, fa[j], fb[j]);
+}
+
 __device__ __forceinline__ void gram_tiles(const RowSet& X, const uint64_t* sk, int mc, float* G) {
   const int lane = lane_id();
   const int nb = (mc + 31) / 32;
   const int Q = X.Q;
-  const int Qe = Q & ~1;  // chunks read in pairs; an odd last chunk is done apart
+  const int NS = Q / 8;  // whole steps; the rest in pairs, an odd last chunk apart
   const int h = lane >> 5;
   for (int I = 0; I < nb; I++) {
     const int ra = 32 * I + (lane & 31);
@@ -448,33 +463,27 @@ __device__ __forceinline__ void gram_tiles(const RowSet& X, const uint64_t* sk, 
       gram_f32x16 acc;
 #pragma unroll
       for (int e = 0; e < 16; e++) acc[e] = 0.0f;
-      float4 fa[kGramPF], fb[kGramPF];
-#pragma unroll
-      for (int u = 0; u < kGramPF; u++)
-        if (2 * u < Qe) {
-          fa[u] = *reinterpret_cast<const float4*>(pa + 32 * (size_t)u);
-          fb[u] = *reinterpret_cast<const float4*>(pb + 32 * (size_t)u);
-        }
-      int c = 0;
-      for (; c + 2 * kGramPF <= Qe; c += 2 * kGramPF) {
-#pragma unroll
-        for (int u = 0; u < kGramPF; u++) {
-          gram_mfma4(acc, fa[u], fb[u]);
-          const int nx = c + 2 * (u + kGramPF);
-          if (nx < Qe) {
-            fa[u] = *reinterpret_cast<const float4*>(pa + 16 * (size_t)nx);
-            fb[u] = *reinterpret_cast<const float4*>(pb + 16 * (size_t)nx);
-          }
-        }
+      float4 a0[4], b0[4], a1[4], b1[4];
+      if (NS > 0) gram_step_load(a0, b0, pa, pb, 0);
+      int s = 0;
+      for (; s + 1 < NS; s += 2) {
+        gram_step_load(a1, b1, pa, pb, s + 1);
+        gram_step_mfma(acc, a0, b0);
+        if (s + 2 < NS) gram_step_load(a0, b0, pa, pb, s + 2);
+        gram_step_mfma(acc, a1, b1);
       }
-#pragma unroll
-      for (int u = 0; u < kGramPF; u++)
-        if (c + 2 * u < Qe) gram_mfma4(acc, fa[u], fb[u]);
-      if (Q & 1) {  // the last chunk: lanes of the upper half contribute zero
+      if (s < NS) gram_step_mfma(acc, a0, b0);
+      int c = 8 * NS;
+      for (; c + 1 < Q; c += 2) {
+        const float4 a = *reinterpret_cast<const float4*>(pa + 16 * (size_t)c);
+        const float4 b = *reinterpret_cast<const float4*>(pb + 16 * (size_t)c);
+        gram_mfma4(acc, a, b);
+      }
+      if (c < Q) {  // the last chunk: lanes of the upper half contribute zero
         float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f), b = a;
         if (h == 0) {
-          a = *reinterpret_cast<const float4*>(pa + 16 * (size_t)Qe);
-          b = *reinterpret_cast<const float4*>(pb + 16 * (size_t)Qe);
+          a = *reinterpret_cast<const float4*>(pa + 16 * (size_t)c);
+          b = *reinterpret_cast<const float4*>(pb + 16 * (size_t)c);
         }
         gram_mfma4(acc, a, b);
       }
@@ -497,22 +506,23 @@ __device__ __forceinline__ void gram_mfma_split(gram_f32x16& acc, const gram_bf1
   acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
 }
 
-// gram_tiles from the split planes: <a,c> ~ <ah,ch> + <ah,cl> + <al,ch>
-// (the dropped <al,cl> and the residuals e are covered by the margin).  A
+// gram_tiles from the split rows: <a,c> ~ <ah,ch> + <ah,cl> + <al,ch> (the
+// dropped <al,cl> and the residuals e are covered by the margin).  A
 // 16-element step is one 32x32x16 product per term: lane l reads the eight
-// k-values at bytes 16 (l >> 5) of the step.  Same accumulator layout and
-// stores as gram_tiles.
+// k-values at bytes 16 (l >> 5) of the step's hi and lo halves, so lanes l
+// and l + 32 together take the step's whole 64 bytes of the row.  Same
+// accumulator layout and stores as gram_tiles.
 __device__ __forceinline__ void gram_tiles_split(const GramSplit& gs, const uint64_t* sk, int mc, float* G) {
   const int lane = lane_id();
   const int nb = (mc + 31) / 32;
-  const int K = (int)(gs.stride / 32);
-  const size_t ho = 16 * (size_t)(lane >> 5);
+  const int K = (int)(gs.stride / 64);
+  const uint8_t* base = gs.p + 16 * (size_t)(lane >> 5);
   for (int I = 0; I < nb; I++) {
     const int ra = 32 * I + (lane & 31);
-    const size_t oa = (size_t)key_id(sk[ra < mc ? ra : 0]) * gs.stride + ho;
+    const size_t oa = (size_t)key_id(sk[ra < mc ? ra : 0]) * gs.stride;
     for (int J = I; J < nb; J++) {
       const int rb = 32 * J + (lane & 31);
-      const size_t ob = (size_t)key_id(sk[rb < mc ? rb : 0]) * gs.stride + ho;
+      const size_t ob = (size_t)key_id(sk[rb < mc ? rb : 0]) * gs.stride;
       gram_f32x16 acc;
 #pragma unroll
       for (int e = 0; e < 16; e++) acc[e] = 0.0f;
@@ -520,10 +530,10 @@ __device__ __forceinline__ void gram_tiles_split(const GramSplit& gs, const uint
 #pragma unroll
       for (int u = 0; u < kGramPF16; u++)
         if (u < K) {
-          ah[u] = *reinterpret_cast<const gram_bf16x8*>(gs.hi + oa + 32 * (size_t)u);
-          al[u] = *reinterpret_cast<const gram_bf16x8*>(gs.lo + oa + 32 * (size_t)u);
-          bh[u] = *reinterpret_cast<const gram_bf16x8*>(gs.hi + ob + 32 * (size_t)u);
-          bl[u] = *reinterpret_cast<const gram_bf16x8*>(gs.lo + ob + 32 * (size_t)u);
+          ah[u] = *reinterpret_cast<const gram_bf16x8*>(base + oa + 64 * (size_t)u);
+          al[u] = *reinterpret_cast<const gram_bf16x8*>(base + oa + 64 * (size_t)u + 32);
+          bh[u] = *reinterpret_cast<const gram_bf16x8*>(base + ob + 64 * (size_t)u);
+          bl[u] = *reinterpret_cast<const gram_bf16x8*>(base + ob + 64 * (size_t)u + 32);
         }
       int c = 0;
       for (; c + kGramPF16 <= K; c += kGramPF16) {
@@ -532,10 +542,10 @@ __device__ __forceinline__ void gram_tiles_split(const GramSplit& gs, const uint
           gram_mfma_split(acc, ah[u], al[u], bh[u], bl[u]);
           const int nx = c + u + kGramPF16;
           if (nx < K) {
-            ah[u] = *reinterpret_cast<const gram_bf16x8*>(gs.hi + oa + 32 * (size_t)nx);
-            al[u] = *reinterpret_cast<const gram_bf16x8*>(gs.lo + oa + 32 * (size_t)nx);
-            bh[u] = *reinterpret_cast<const gram_bf16x8*>(gs.hi + ob + 32 * (size_t)nx);
-            bl[u] = *reinterpret_cast<const gram_bf16x8*>(gs.lo + ob + 32 * (size_t)nx);
+            ah[u] = *reinterpret_cast<const gram_bf16x8*>(base + oa + 64 * (size_t)nx);
+            al[u] = *reinterpret_cast<const gram_bf16x8*>(base + oa + 64 * (size_t)nx + 32);
+            bh[u] = *reinterpret_cast<const gram_bf16x8*>(base + ob + 64 * (size_t)nx);
+            bl[u] = *reinterpret_cast<const gram_bf16x8*>(base + ob + 64 * (size_t)nx + 32);
           }
         }
       }
@@ -943,7 +953,7 @@ k_beam(BeamArgs A) {
           gram = A.gram != nullptr && mc <= kGramMax && wslot < kGramSlots;
         if (gram) {
           float* G = A.gram + (size_t)wslot * kGramMax * kGramMax;
-          if (A.split.hi)
+          if (A.split.p)
             gram_tiles_split(A.split, sk, mc, G);
           else
             gram_tiles(X, sk, mc, G);
@@ -952,7 +962,7 @@ k_beam(BeamArgs A) {
           // stores visible and drop stale lines before reading them back
           __threadfence();
           FG_TICK(8);
-          kept = prune_gram<DK, L, NCH>(X, A.d, A.split.hi != nullptr, A.alpha, A.R, sk, mc, G, S.alive, S.cid,
+          kept = prune_gram<DK, L, NCH>(X, A.d, A.split.p != nullptr, A.alpha, A.R, sk, mc, G, S.alive, S.cid,
                                         S.ckey, out, &my_pe, &my_rc);
         } else
           kept = prune_wave<DK, L, NCH>(X, A.alpha, A.R, sk, mc, S.alive, S.cid, S.ckey, out, &my_pe);

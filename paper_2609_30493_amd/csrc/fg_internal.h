@@ -46,8 +46,11 @@ void* pick_screen_fp8(int dk, int Q, int ef, int hslots);
 // Narrow copies for the screened harvest (fg_screen.hip): row stride in
 // bytes, and the copy with its per-row error norm, norm and fp8 factor.
 int64_t screen_stride(int d, int screen);
+// xs may be NULL (no plain copy); sp (bfloat16 only, may be NULL) receives
+// the interleaved hi/lo split, rows split_stride(d) bytes apart.
+int64_t split_stride(int d);
 hipError_t make_screen(const Shape& s, int screen, uint8_t* xs, float* err, float* norm, float* sinv,
-                       hipStream_t st, uint8_t* xs_lo = nullptr);
+                       hipStream_t st, uint8_t* sp = nullptr);
 
 // Small utilities (fg_graph.hip).
 hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t st);
@@ -119,7 +122,7 @@ struct FinalizeArgs {
   uint32_t* nmid;  // their count (device, zero on entry)
   int d;
   float* gram;     // float32 rows longer than 256 elements: Gram scratch per block (or NULL)
-  GramSplit split; // the Gram tiles from the bfloat16 split (hi NULL: from the rows)
+  GramSplit split; // the Gram tiles from the bfloat16 split (p NULL: from the rows)
 };
 struct FinalizeBig {
   KSeg* segs;

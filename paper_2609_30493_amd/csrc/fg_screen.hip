@@ -9,9 +9,11 @@
 // code * 2^-k.  For every row the norm of the actual error |u^ - u| and the
 // norm |u| are accumulated in float64 and rounded up to float32, so the
 // margin the search uses bounds the copy that the search reads, whatever
-// rounding the conversion did.  For bfloat16 an optional second plane holds
-// each element's remainder x - hi rounded to bfloat16 (lo), so that
-// hi + lo carries 16 significant bits: the prune tiles use both.
+// rounding the conversion did.  For bfloat16 an optional split copy holds
+// hi and each element's remainder x - hi rounded to bfloat16 (lo), so that
+// hi + lo carries 16 significant bits, interleaved per 16-element step (32
+// bytes of hi, then 32 of lo): the prune tiles read both halves of a step
+// from one 64-byte span.
 #include "fg_internal.h"
 
 namespace fg {
@@ -47,7 +49,7 @@ __device__ __forceinline__ uint16_t bf16_rne(float f) {
 template <int SCR>
 __global__ void __launch_bounds__(256) k_make_screen(const uint8_t* x, int64_t stride, int64_t n, int d,
                                                      uint8_t* xs, int64_t xs_stride, float* err, float* norm,
-                                                     float* sinv, uint8_t* xs_lo) {
+                                                     float* sinv, uint8_t* sp, int64_t sp_stride) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -89,15 +91,17 @@ __global__ void __launch_bounds__(256) k_make_screen(const uint8_t* x, int64_t s
         uint2 w;
         w.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
         w.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
-        *reinterpret_cast<uint2*>(xs + i * xs_stride + 8 * (int64_t)c) = w;
-        if (xs_lo) {  // the remainder x - hi (exact in float32), rounded to bfloat16
+        if (xs) *reinterpret_cast<uint2*>(xs + i * xs_stride + 8 * (int64_t)c) = w;
+        if (sp) {  // the remainder x - hi (exact in float32), rounded to bfloat16
           uint16_t lo[4];
 #pragma unroll
           for (int t = 0; t < 4; t++) lo[t] = bf16_rne(a[t] - back[t]);
           uint2 wl;
           wl.x = (uint32_t)lo[0] | ((uint32_t)lo[1] << 16);
           wl.y = (uint32_t)lo[2] | ((uint32_t)lo[3] << 16);
-          *reinterpret_cast<uint2*>(xs_lo + i * xs_stride + 8 * (int64_t)c) = wl;
+          uint8_t* at = sp + i * sp_stride + 64 * (int64_t)(c >> 2) + 8 * (c & 3);
+          *reinterpret_cast<uint2*>(at) = w;
+          *reinterpret_cast<uint2*>(at + 32) = wl;
         }
       } else {
         int w = __builtin_amdgcn_cvt_pk_fp8_f32(a[0] * scale, a[1] * scale, 0, false);
@@ -117,11 +121,16 @@ __global__ void __launch_bounds__(256) k_make_screen(const uint8_t* x, int64_t s
         n2 += (double)a[t] * (double)a[t];
       }
     }
-    if constexpr (SCR == SCR_BF16) {  // zero the row's padding (read by 16-element steps)
-      for (int64_t c = C + lane; c < xs_stride / 8; c += 64) {
-        *reinterpret_cast<uint2*>(xs + i * xs_stride + 8 * c) = make_uint2(0, 0);
-        if (xs_lo) *reinterpret_cast<uint2*>(xs_lo + i * xs_stride + 8 * c) = make_uint2(0, 0);
-      }
+    if constexpr (SCR == SCR_BF16) {  // zero the padding (read by 16-element steps)
+      if (xs)
+        for (int64_t c = C + lane; c < xs_stride / 8; c += 64)
+          *reinterpret_cast<uint2*>(xs + i * xs_stride + 8 * c) = make_uint2(0, 0);
+      if (sp)
+        for (int64_t c = C + lane; c < sp_stride / 16; c += 64) {
+          uint8_t* at = sp + i * sp_stride + 64 * (c >> 2) + 8 * (c & 3);
+          *reinterpret_cast<uint2*>(at) = make_uint2(0, 0);
+          *reinterpret_cast<uint2*>(at + 32) = make_uint2(0, 0);
+        }
     }
     e2 = wave_sum_f64(e2);
     n2 = wave_sum_f64(n2);
@@ -141,18 +150,20 @@ int64_t screen_stride(int d, int screen) {
   return ((int64_t)d + 15) / 16 * 16;
 }
 
+int64_t split_stride(int d) { return (4 * (int64_t)d + 63) / 64 * 64; }
+
 hipError_t make_screen(const Shape& s, int screen, uint8_t* xs, float* err, float* norm, float* sinv,
-                       hipStream_t st, uint8_t* xs_lo) {
+                       hipStream_t st, uint8_t* sp) {
   const int64_t xst = screen_stride(s.d, screen);
   int64_t blocks = (s.n + 3) / 4;
   if (blocks > 65536) blocks = 65536;
   if (blocks < 1) blocks = 1;
   if (screen == SCR_BF16)
     k_make_screen<SCR_BF16><<<(unsigned)blocks, 256, 0, st>>>(s.x, s.stride, s.n, s.d, xs, xst, err, norm, sinv,
-                                                              xs_lo);
+                                                              sp, split_stride(s.d));
   else
     k_make_screen<SCR_FP8><<<(unsigned)blocks, 256, 0, st>>>(s.x, s.stride, s.n, s.d, xs, xst, err, norm, sinv,
-                                                             nullptr);
+                                                             nullptr, 0);
   return hipGetLastError();
 }
 
