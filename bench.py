@@ -237,7 +237,8 @@ def screen_compare(args):
                 wall = time.perf_counter() - t0
                 assert F.graph_hash(G) == hashes[F.SCREEN_NONE]
                 res[f].append(dict(harvest_ms=t["harvest_ms"], build_s=wall, screen_ms=t["screen_ms"],
-                                   finalize_ms=t["finalize_ms"], evals=c["harvest_evals"],
+                                   finalize_ms=t["finalize_ms"], scaffold_ms=t["scaffold_ms"],
+                                   evals=c["harvest_evals"],
                                    rejected=c["screen_rejected"], rechecks=c["prune_rechecks"]))
                 log(f"[screen] rep {rep} form {f}: harvest {t['harvest_ms']:.0f} ms build {wall:.2f} s")
         row = {"workload": w.name, "n": n, "d": w.d, "metric": metric, "graph_hash": f"{hashes[0]:#018x}",
@@ -258,6 +259,7 @@ def screen_compare(args):
                  "bytes_per_eval": narrow + (1 - rej / ev) * row_bytes if f else row_bytes,
                  "screen_copy_ms": float(np.median([r["screen_ms"] for r in res[f]])),
                  "finalize_ms_median": float(np.median([r["finalize_ms"] for r in res[f]])),
+                 "scaffold_ms_median": float(np.median([r["scaffold_ms"] for r in res[f]])),
                  "prune_rechecks": int(res[f][0]["rechecks"])}
             if f:
                 lr_h, lr_b = np.log(base_h / h), np.log(base_b / b)

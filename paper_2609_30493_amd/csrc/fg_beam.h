@@ -448,11 +448,40 @@ __device__ __forceinline__ void gram_step_mfma(gram_f32x16& acc, const float4* f
   for (int j = 0; j < 4; j++) gram_mfma4(acc, fa[j], fb[j]);
 }
 
+// acc += the 32x32 tile <a_i, b_j>: lane l reads row a_(l & 31) at pa and
+// row b_(l & 31) at pb (both already offset by 16 (l >> 5) bytes), Q chunks.
+__device__ __forceinline__ void gram_tile_acc(gram_f32x16& acc, const uint8_t* pa, const uint8_t* pb, int Q) {
+  const int h = lane_id() >> 5;
+  const int NS = Q / 8;  // whole steps; the rest in pairs, an odd last chunk apart
+  float4 a0[4], b0[4], a1[4], b1[4];
+  if (NS > 0) gram_step_load(a0, b0, pa, pb, 0);
+  int s = 0;
+  for (; s + 1 < NS; s += 2) {
+    gram_step_load(a1, b1, pa, pb, s + 1);
+    gram_step_mfma(acc, a0, b0);
+    if (s + 2 < NS) gram_step_load(a0, b0, pa, pb, s + 2);
+    gram_step_mfma(acc, a1, b1);
+  }
+  if (s < NS) gram_step_mfma(acc, a0, b0);
+  int c = 8 * NS;
+  for (; c + 1 < Q; c += 2) {
+    const float4 a = *reinterpret_cast<const float4*>(pa + 16 * (size_t)c);
+    const float4 b = *reinterpret_cast<const float4*>(pb + 16 * (size_t)c);
+    gram_mfma4(acc, a, b);
+  }
+  if (c < Q) {  // the last chunk: lanes of the upper half contribute zero
+    float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f), b = a;
+    if (h == 0) {
+      a = *reinterpret_cast<const float4*>(pa + 16 * (size_t)c);
+      b = *reinterpret_cast<const float4*>(pb + 16 * (size_t)c);
+    }
+    gram_mfma4(acc, a, b);
+  }
+}
+
 __device__ __forceinline__ void gram_tiles(const RowSet& X, const uint64_t* sk, int mc, float* G) {
   const int lane = lane_id();
   const int nb = (mc + 31) / 32;
-  const int Q = X.Q;
-  const int NS = Q / 8;  // whole steps; the rest in pairs, an odd last chunk apart
   const int h = lane >> 5;
   for (int I = 0; I < nb; I++) {
     const int ra = 32 * I + (lane & 31);
@@ -463,30 +492,7 @@ __device__ __forceinline__ void gram_tiles(const RowSet& X, const uint64_t* sk, 
       gram_f32x16 acc;
 #pragma unroll
       for (int e = 0; e < 16; e++) acc[e] = 0.0f;
-      float4 a0[4], b0[4], a1[4], b1[4];
-      if (NS > 0) gram_step_load(a0, b0, pa, pb, 0);
-      int s = 0;
-      for (; s + 1 < NS; s += 2) {
-        gram_step_load(a1, b1, pa, pb, s + 1);
-        gram_step_mfma(acc, a0, b0);
-        if (s + 2 < NS) gram_step_load(a0, b0, pa, pb, s + 2);
-        gram_step_mfma(acc, a1, b1);
-      }
-      if (s < NS) gram_step_mfma(acc, a0, b0);
-      int c = 8 * NS;
-      for (; c + 1 < Q; c += 2) {
-        const float4 a = *reinterpret_cast<const float4*>(pa + 16 * (size_t)c);
-        const float4 b = *reinterpret_cast<const float4*>(pb + 16 * (size_t)c);
-        gram_mfma4(acc, a, b);
-      }
-      if (c < Q) {  // the last chunk: lanes of the upper half contribute zero
-        float4 a = make_float4(0.0f, 0.0f, 0.0f, 0.0f), b = a;
-        if (h == 0) {
-          a = *reinterpret_cast<const float4*>(pa + 16 * (size_t)c);
-          b = *reinterpret_cast<const float4*>(pb + 16 * (size_t)c);
-        }
-        gram_mfma4(acc, a, b);
-      }
+      gram_tile_acc(acc, pa, pb, X.Q);
 #pragma unroll
       for (int r = 0; r < 16; r++) {
         const int i = 32 * I + gram_acc_row(r, lane);

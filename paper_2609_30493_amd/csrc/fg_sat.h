@@ -50,11 +50,16 @@ struct SatArgs {
   uint32_t* n_next;
   uint32_t* n_small;
   int* status;
+  // float32 rows of more than 256 elements: |x_i|^2 of every row (any
+  // float32 summation order), for the matrix-core closest-neighbour
+  // assignment (NULL: exact streaming assignment only)
+  const float* norm;
+  int d;
 };
 
 struct SatWs {
   size_t perm, perm2, key, key2, flag, owner, nl, ccount, coff, stk_a, stk_s, stk_m, stk_tmp;
-  size_t segs, next, small, tiles, ctl, total;
+  size_t segs, next, small, tiles, ctl, norm, total;
   uint32_t cap_segs, cap_small, cap_tiles;
 };
 

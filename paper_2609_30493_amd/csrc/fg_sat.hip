@@ -298,11 +298,96 @@ __device__ void argmin_wave(const RowSet& X, const uint32_t* cand, int ncand, co
   wave_sync();
 }
 
+// argmin_wave for float32 rows of more than 64 chunks, from 32x32 tiles of
+// <v, b> on the matrix cores: d~(v,b) = |v|^2 + |b|^2 - 2<v,b> (cosine
+// 1 - <v,b>) with the Gram-tile prune's margin eps.  Scanning the neighbours
+// in 32-column blocks, each row keeps U = the least fl(d~ + eps) so far (an
+// upper bound on its exact minimum); a pair whose fl(d~ - eps) is at most U
+// might be the minimum and is queued.  U only falls, so every pair within
+// the final bound is queued.  Queued pairs get the exact declared-order
+// distance and the least key (distance, neighbour id) wins, as in
+// argmin_wave.  LDS: best[64], qi[64], qj[64].
+template <int DK, int L, int NCH>
+__device__ void argmin_gram(const RowSet& X, int d, const float* norm, const uint32_t* cand, int ncand,
+                            const uint32_t* nbr, int nn, uint32_t* owner_out, unsigned long long* ev,
+                            uint64_t* best, uint32_t* qi, uint32_t* qj) {
+  constexpr int G = 64 / L;
+  const int lane = lane_id(), h = lane >> 5, g = lane % L;
+  const float u8 = 8.0f * 5.9604645e-08f;
+  best[lane] = FG_KEY_NONE;
+  wave_sync();
+  int qn = 0;
+  auto flush = [&]() {
+    for (int e0 = 0; e0 < qn; e0 += G) {
+      const int e = e0 + lane / L;
+      const int ec = e < qn ? e : 0;
+      const uint32_t v = cand[qi[ec]], b = nbr[qj[ec]];
+      const float dist = group_dist_stream<DK, L, NCH>(X.x + (size_t)v * X.stride, X.x + (size_t)b * X.stride,
+                                                        X.Q, g);
+      if (e < qn && g == 0) atomicMin(reinterpret_cast<unsigned long long*>(&best[qi[e]]),
+                                      (unsigned long long)make_key(f32_to_ord(dist), b));
+    }
+    wave_sync();
+    for (int e = lane; e < qn; e += 64)
+      if (key_id(best[qi[e]]) == nbr[qj[e]]) owner_out[qi[e]] = qj[e];
+    wave_sync();
+    qn = 0;
+  };
+  for (int I = 0; 32 * I < ncand; I++) {
+    const int ra = 32 * I + (lane & 31);
+    const uint8_t* pa = X.x + (size_t)cand[ra < ncand ? ra : 0] * X.stride + 16 * h;
+    float na[16], U[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+      const int i = 32 * I + gram_acc_row(r, lane);
+      na[r] = norm[cand[i < ncand ? i : 0]];
+      U[r] = __builtin_inff();
+    }
+    for (int J = 0; 32 * J < nn; J++) {
+      const int jb = 32 * J + (lane & 31);
+      const uint32_t b = nbr[jb < nn ? jb : 0];
+      const float nb = norm[b];
+      gram_f32x16 acc;
+#pragma unroll
+      for (int e = 0; e < 16; e++) acc[e] = 0.0f;
+      gram_tile_acc(acc, pa, X.x + (size_t)b * X.stride + 16 * h, X.Q);
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        const int i = 32 * I + gram_acc_row(r, lane);
+        const bool ok = jb < nn && i < ncand;
+        const float dt = DK == F32L2 ? (na[r] + nb) - 2.0f * acc[r] : 1.0f - acc[r];
+        const float eps = gram_eps<DK>(dt, na[r], nb, d, false);
+        const float up = dt + eps, lo = dt - eps;
+        float m = ok ? up + fabsf(up) * u8 : __builtin_inff();
+#pragma unroll
+        for (int off = 16; off >= 1; off >>= 1) m = fminf(m, __shfl_xor(m, off, 64));
+        U[r] = fminf(U[r], m);
+        const bool maybe = ok && lo - fabsf(lo) * u8 <= U[r];
+        const uint64_t mq = ballot(maybe);
+        const int nq = popc64(mq);
+        if (nq == 0) continue;
+        if (qn + nq > 64) flush();
+        if (maybe) {
+          const int pos = qn + popc64(mq & lanes_below());
+          qi[pos] = (uint32_t)i;
+          qj[pos] = (uint32_t)jb;
+        }
+        qn += nq;
+        wave_sync();
+      }
+    }
+  }
+  if (qn) flush();
+  *ev += (unsigned long long)ncand * nn;
+}
+
 template <int DK, int L, int NCH>
 __global__ void __launch_bounds__(64) k_sat_assign(SatArgs A) {
   __shared__ uint32_t cand[64];
   __shared__ uint32_t cpos[64];
   __shared__ uint32_t own[64];
+  __shared__ uint64_t gbest[64];
+  __shared__ uint32_t gqi[64], gqj[64];
   const int lane = lane_id();
   const SatTile tl = A.tiles[blockIdx.x];
   const SatSeg sg = A.segs[tl.seg];
@@ -320,7 +405,12 @@ __global__ void __launch_bounds__(64) k_sat_assign(SatArgs A) {
     }
     wave_sync();
     int cnt = popc64(m);
-    argmin_wave<DK, L, NCH>(A.X, cand, cnt, A.nl + sg.start, (int)sg.nN, own, &ev);
+    bool gram = false;
+    if constexpr (DK != U8L2 && NCH >= 16) gram = A.norm != nullptr;
+    if (gram)
+      argmin_gram<DK, L, NCH>(A.X, A.d, A.norm, cand, cnt, A.nl + sg.start, (int)sg.nN, own, &ev, gbest, gqi, gqj);
+    else
+      argmin_wave<DK, L, NCH>(A.X, cand, cnt, A.nl + sg.start, (int)sg.nN, own, &ev);
     if (lane < cnt) A.owner[sg.start + cpos[lane]] = own[lane];
     wave_sync();
   }
@@ -669,6 +759,30 @@ hipError_t sat_iota(uint32_t* perm, int64_t n, uint32_t T, int64_t off, int64_t 
                     hipStream_t st);
 hipError_t sat_clear_counts(SatArgs& a, unsigned nt, hipStream_t st);
 
+namespace {
+// |x_i|^2 of every float32 row, one wave per row (four elements per lane
+// step, then a wave sum).
+__global__ void __launch_bounds__(256) k_sat_norms(const uint8_t* x, int64_t stride, int64_t n, int Q,
+                                                   float* out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t i = w0; i < n; i += nw) {
+    float s = 0.0f;
+    for (int c = lane; c < Q; c += 64) {
+      const float4 v = *reinterpret_cast<const float4*>(x + i * stride + 16 * (int64_t)c);
+      s = __builtin_fmaf(v.x, v.x, s);
+      s = __builtin_fmaf(v.y, v.y, s);
+      s = __builtin_fmaf(v.z, v.z, s);
+      s = __builtin_fmaf(v.w, v.w, s);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) out[i] = s;
+  }
+}
+}  // namespace
+
 size_t sat_workspace_bytes(int64_t n, uint32_t T, SatWs* w) {
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -698,6 +812,7 @@ size_t sat_workspace_bytes(int64_t n, uint32_t T, SatWs* w) {
   w->cap_tiles = (uint32_t)(tn / kTile + 2 * w->cap_segs + 64);
   w->tiles = take((size_t)w->cap_tiles * sizeof(SatTile));
   w->ctl = take(4096);
+  w->norm = take((uint64_t)n * 4);
   w->total = o;
   return o;
 }
@@ -749,6 +864,7 @@ hipError_t sat_build_multi(const Shape& s, uint32_t T, const std::vector<SatInst
   a.n_next = &ctl->n_next;
   a.n_small = &ctl->n_small;
   a.status = &ctl->status;
+  a.d = s.d;
   hipError_t e;
 #define CK(x)                       \
   do {                              \
@@ -760,6 +876,12 @@ hipError_t sat_build_multi(const Shape& s, uint32_t T, const std::vector<SatInst
   CK(fill_u32(reinterpret_cast<uint32_t*>(ctl), 0, sizeof(SatCtl) / 4, st));
   CK(fill_u32(parent, FG_NONE, (int64_t)tn, st));
   CK(fill_u32(a.ccount, 0, (int64_t)tn, st));
+  if (s.dk != U8L2 && s.Q > 64 && s.d <= 1024) {  // the matrix-core assignment's norms
+    float* nrm = reinterpret_cast<float*>(ws + w.norm);
+    k_sat_norms<<<(unsigned)blocks_for(n, 4), 256, 0, st>>>(s.x, s.stride, n, s.Q, nrm);
+    CK(hipGetLastError());
+    a.norm = nrm;
+  }
   // Tree t of instance i: its first bag at positions [t*n + off, t*n + off +
   // n_i - 1) holds every id of the instance but its root.
   std::vector<SatSeg> large, init_small;
