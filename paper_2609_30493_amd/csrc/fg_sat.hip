@@ -606,7 +606,12 @@ __global__ void __launch_bounds__(64) k_sat_small(SatArgs A, uint32_t nsmall) {
         wave_sync();
         int cnt = popc64(msk);
         if (cnt) {
-          argmin_wave<DK, L, NCH>(A.X, cid, cnt, nb, nn, own + nrej, &ev_asg);
+          bool gram = false;
+          if constexpr (DK != U8L2 && NCH >= 16) gram = A.norm != nullptr;
+          if (gram)  // best in ckey, the queue in cc (free until the counts below)
+            argmin_gram<DK, L, NCH>(A.X, A.d, A.norm, cid, cnt, nb, nn, own + nrej, &ev_asg, ckey, cc, cc + 64);
+          else
+            argmin_wave<DK, L, NCH>(A.X, cid, cnt, nb, nn, own + nrej, &ev_asg);
           if (lane < cnt) A.stk_tmp[s + nrej + lane] = cid[lane];  // id of rejected #(nrej + lane)
           nrej += cnt;
         }
