@@ -187,6 +187,100 @@ __global__ void __launch_bounds__(64) k_sat_resolve(SatArgs A) {
   }
 }
 
+// The filter's tests for float32 rows of more than 64 chunks: the cnt
+// candidates (ids in key order of cdk, positions cpos) against the nb new
+// neighbours from 32x32 matrix-core tiles with the Gram-tile prune's margin.
+// A test is decided from d~ when the margin allows (reject when fl(d~ + eps)
+// <= d(v,a), keep when fl(d~ - eps) > d(v,a)), else from the exact
+// declared-order distance; each candidate walks the neighbours in acceptance
+// order to its first rejection, so flags and the test count are those of the
+// exact loop.  dec: LDS [64 * 64] decision codes.
+template <int DK, int L, int NCH>
+__device__ void filter_gram(const SatArgs& A, const SatSeg& sg, int cnt, const uint32_t* nbr, int nb,
+                            const uint32_t* cpos, const uint64_t* cdk, uint8_t* dec, uint32_t* qv,
+                            uint32_t* qb, float* qd, unsigned long long* ev) {
+  constexpr int G = 64 / L;
+  constexpr uint8_t KEEP = 0, REJ = 1, UNSURE = 2;
+  const int lane = lane_id(), h = lane >> 5, g = lane % L;
+  const float u8 = 8.0f * 5.9604645e-08f;
+  const RowSet& X = A.X;
+  for (int I = 0; 32 * I < cnt; I++) {
+    const int ra = 32 * I + (lane & 31);
+    const uint8_t* pa = X.x + (size_t)key_id(cdk[ra < cnt ? ra : 0]) * X.stride + 16 * h;
+    float na[16], dva[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+      const int i = 32 * I + gram_acc_row(r, lane);
+      const uint64_t k = cdk[i < cnt ? i : 0];
+      na[r] = A.norm[key_id(k)];
+      dva[r] = hi_to_float<DK>(key_hi(k));
+    }
+    for (int J = 0; 32 * J < nb; J++) {
+      const int jb = 32 * J + (lane & 31);
+      const uint32_t b = nbr[jb < nb ? jb : 0];
+      const float nbn = A.norm[b];
+      gram_f32x16 acc;
+#pragma unroll
+      for (int e = 0; e < 16; e++) acc[e] = 0.0f;
+      gram_tile_acc(acc, pa, X.x + (size_t)b * X.stride + 16 * h, X.Q);
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        const int i = 32 * I + gram_acc_row(r, lane);
+        if (i < cnt && jb < nb) {
+          const float dt = DK == F32L2 ? (na[r] + nbn) - 2.0f * acc[r] : 1.0f - acc[r];
+          const float eps = gram_eps<DK>(dt, na[r], nbn, A.d, false);
+          const float up = dt + eps, lo = dt - eps;
+          uint8_t c = UNSURE;
+          if (up + fabsf(up) * u8 <= dva[r]) c = REJ;
+          else if (lo - fabsf(lo) * u8 > dva[r]) c = KEEP;
+          dec[i * 64 + jb] = c;
+        }
+      }
+    }
+  }
+  wave_sync();
+  // each candidate (lane) walks its row to the first rejection
+  int j = 0;
+  bool done = lane >= cnt, rej = false;
+  while (true) {
+    if (!done) {
+      while (j < nb && dec[lane * 64 + j] == KEEP) j++;
+      if (j == nb) done = true;
+      else if (dec[lane * 64 + j] == REJ) done = rej = true;
+    }
+    const bool pend = !done;  // at an UNSURE test
+    const uint64_t pm = ballot(pend);
+    if (!pm) break;
+    const int np = popc64(pm);
+    if (pend) {
+      const int q = popc64(pm & lanes_below());
+      qv[q] = key_id(cdk[lane]);
+      qb[q] = nbr[j];
+    }
+    wave_sync();
+    for (int e0 = 0; e0 < np; e0 += G) {
+      const int e = e0 + lane / L;
+      const int ec = e < np ? e : 0;
+      const float v = group_dist_stream<DK, L, NCH>(X.x + (size_t)qv[ec] * X.stride, X.x + (size_t)qb[ec] * X.stride,
+                                                    X.Q, g);
+      if (e < np && g == 0) qd[e] = v;
+    }
+    wave_sync();
+    if (pend) {
+      const float dvb = qd[popc64(pm & lanes_below())];
+      if (dvb <= hi_to_float<DK>(key_hi(cdk[lane]))) done = rej = true;
+      else j++;
+    }
+    wave_sync();
+  }
+  uint32_t tests = lane < cnt ? (uint32_t)(rej ? j + 1 : nb) : 0u;
+  if (lane < cnt && rej) A.flag[sg.start + cpos[lane]] = 2;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) tests += __shfl_xor(tests, off, 64);
+  *ev += tests;  // the same wave total in every lane, as the exact loop counts
+  wave_sync();
+}
+
 // Reject every undecided candidate after the resolved chunk that one of the
 // chunk's new neighbours occludes (d(v,b) <= d(v,a)), testing the new
 // neighbours in acceptance order and stopping at the first that rejects.
@@ -196,12 +290,15 @@ __global__ void __launch_bounds__(64) k_sat_filter(SatArgs A) {
   __shared__ uint64_t ckey[64];
   __shared__ uint32_t cpos[64];
   __shared__ uint64_t cdk[64];
+  __shared__ uint8_t dec[(DK != U8L2 && NCH >= 16) ? 64 * 64 : 1];
   const int lane = lane_id(), g = lane % L;
   const SatTile tl = A.tiles[blockIdx.x];
   const SatSeg sg = A.segs[tl.seg];
   if (sg.nN == sg.nN_prev) return;
   const uint32_t lo = max(tl.off, sg.pos), hi = min(sg.len, tl.off + kTile);
   unsigned long long ev = 0;
+  bool gram = false;
+  if constexpr (DK != U8L2 && NCH >= 16) gram = A.norm != nullptr && sg.nN - sg.nN_prev <= 64;
   for (uint32_t base = lo; base < hi; base += 64) {
     uint32_t j = base + lane;
     bool und = j < hi && A.flag[sg.start + j] == 0;
@@ -214,6 +311,14 @@ __global__ void __launch_bounds__(64) k_sat_filter(SatArgs A) {
     }
     wave_sync();
     int cnt = popc64(m);
+    if constexpr (DK != U8L2 && NCH >= 16) {
+      if (gram) {  // queue in cid and ckey (ids, then distances), decisions in dec
+        filter_gram<DK, L, NCH>(A, sg, cnt, A.nl + sg.start + sg.nN_prev, (int)(sg.nN - sg.nN_prev), cpos, cdk,
+                                dec, cid, reinterpret_cast<uint32_t*>(ckey), reinterpret_cast<float*>(ckey) + 64,
+                                &ev);
+        continue;
+      }
+    }
     for (uint32_t kb = sg.nN_prev; kb < sg.nN && cnt > 0; kb++) {
       uint32_t b = A.nl[sg.start + kb];
       Chunks<L, NCH> bc;
