@@ -309,6 +309,16 @@ fg_status fg_autotune(const fg_data* data, const fg_params* params,
                       void* stream, fg_params* tuned);
 
 /* Message of the last failed call on this thread ("" if none). */
+/* Device-side status of the last call made with workspace ws_dev, for
+ * workspaces sized by fg_workspace_size() or fg_batched_workspace_size()
+ * (each entry point taking one clears the status when it starts; not for
+ * the fg_leaf_knn workspace): synchronises `stream`, then returns
+ * FG_ECAPACITY if that call overflowed a bounded device buffer (the expanded
+ * set of a search), else FG_OK.  fg_harvest_block and fg_finalize without
+ * counters return before their kernels finish; this call reports what they
+ * found (Sec. 3 bounds nothing: the capacities are this library's). */
+fg_status fg_sync_status(void* ws_dev, void* stream);
+
 const char* fg_last_error(void);
 
 #ifdef __cplusplus

@@ -496,6 +496,17 @@ fg_status fg_screen_copy(const fg_data* data, uint32_t screen, void* xs_dev, flo
   return FG_OK;
 }
 
+fg_status fg_sync_status(void* ws_dev, void* stream) {
+  if (!ws_dev) return set_error("ws_dev is NULL"), FG_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int status = 0;
+  // the control block is the first region of every workspace layout
+  FG_HIP(hipMemcpyAsync(&status, static_cast<char*>(ws_dev) + offsetof(Ctl, status), sizeof(int),
+                        hipMemcpyDeviceToHost, st));
+  FG_HIP(hipStreamSynchronize(st));
+  return status_error(status);
+}
+
 size_t fg_workspace_size(const fg_data* data, const fg_params* params) {
   if (!data || data->n < 1) return 0;
   return ws_map(data->n, params, data->d).total;

@@ -91,6 +91,7 @@ _SIGS = {
     "fg_search": (C.c_int, [P, P, P, C.c_int64, C.c_uint32, C.c_uint32, P, P, P, P,
                             C.c_size_t, P]),
     "fg_graph_hash": (C.c_int, [P, P, P]),
+    "fg_sync_status": (C.c_int, [P, P]),
     "fg_autotune": (C.c_int, [P, P, C.c_char_p, P, C.c_size_t, P, P]),
     "fg_batched_workspace_size": (C.c_size_t, [P, P, C.c_uint32]),
     "fg_build_graph_batched": (C.c_int, [P, P, P, C.c_uint32, P, P, C.c_size_t, P, C.c_int, P]),
@@ -295,6 +296,12 @@ def build_graph_batched(datas, paramses, seeds, graphs, ws=None, use_hipgraph=Fa
     _check(lib().fg_build_graph_batched(_ptr_array(datas), _ptr_array(paramses), sd, count, _ptr_array(graphs),
                                         wp, wn, _stream(stream), 1 if use_hipgraph else 0, C.byref(c)))
     return c.as_dict(), ws
+
+
+def sync_status(ws: torch.Tensor, stream=None) -> None:
+    """Wait for the last call made with workspace ws; raise FgError if it
+    overflowed a bounded device buffer."""
+    _check(lib().fg_sync_status(_ptr(ws), _stream(stream)))
 
 
 def graph_hash(graph: fg_graph, stream=None) -> int:

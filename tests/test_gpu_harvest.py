@@ -96,6 +96,15 @@ def test_harvest_spill_path_and_full_width(fgo):
     # run again on the same workspace: the spill bitsets must have been left clean
     cg2 = F.harvest_block(data, F.csr(dev(off), dev(ids)), dev(r), params, 7, rows, cnt, ws)
     assert cg2["harvest_evals"] == co["harvest_evals"]
+    # without counters the call returns at once; fg_sync_status waits and
+    # reports the device status (clean here)
+    rows.fill_(-1)
+    F.harvest_block(data, F.csr(dev(off), dev(ids)), dev(r), params, 7, rows, cnt, ws, counters=False)
+    F.sync_status(ws)
+    assert np.array_equal(host_u32(rows), rows_o)
+    with pytest.raises(F.FgError) as e:
+        F._check(F.lib().fg_sync_status(None, None))
+    assert e.value.code == F.FG_EINVAL
 
 
 def test_harvest_rejects_bad_arguments():
