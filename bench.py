@@ -246,8 +246,8 @@ def screen_compare(args):
         base_h = np.array([r["harvest_ms"] for r in res[0]])
         base_b = np.array([r["build_s"] for r in res[0]])
         row_bytes = 4 * w.d
-        names = {0: "fp32", 1: "bf16", 2: "fp8e4m3", 3: "bf16split_prune"}
-        for f, name in ((f, names[f]) for f in forms):
+        form_names = {0: "fp32", 1: "bf16", 2: "fp8e4m3", 3: "bf16split_prune"}
+        for f, name in ((f, form_names[f]) for f in forms):
             h = np.array([r["harvest_ms"] for r in res[f]])
             b = np.array([r["build_s"] for r in res[f]])
             ev = res[f][0]["evals"]
