@@ -133,7 +133,7 @@ struct BeamArgs {
   GramSplit split;
 };
 
-constexpr int kGramMax = 256;    // candidates the Gram-tile prune takes
+constexpr int kGramMax = 1024;   // candidates the Gram-tile prune takes
 constexpr int kGramPF16 = 4;     // split-tile steps in flight
 constexpr int kGramSlots = 2048; // wave slots that have Gram scratch
 
