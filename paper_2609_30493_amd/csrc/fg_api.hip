@@ -115,6 +115,7 @@ struct WsMap {
   size_t xsp;                               // the bfloat16 split (interleaved hi/lo)
   int64_t xsp_stride;
   size_t gram;                              // Gram-tile prune scratch (float32, d > 256)
+  size_t norm;                              // |x_i|^2 per row for it
   int64_t xs_stride;
   SatWs satw;
   size_t total;
@@ -171,7 +172,10 @@ WsMap ws_map(int64_t n, const fg_params* p, int d = 0) {
   m.roots = take(64 * 4);
   sat_workspace_bytes(n, (uint32_t)T, &m.satw);
   m.sat = take(m.satw.total);
-  if (p && d > 256 && d % 4 == 0 && d <= 1024) m.gram = take((size_t)kGramSlots * kGramMax * kGramMax * 4);
+  if (p && d > 256 && d % 4 == 0 && d <= 1024) {
+    m.gram = take((size_t)kGramSlots * kGramMax * kGramMax * 4);
+    m.norm = take(un * 4);
+  }
   if (p && p->screen && d > 0) {
     m.xs_stride = screen_stride(d, copy_kind(p->screen));
     if (search_screen(p->screen) != SCR_NONE) m.xs = take(un * (uint64_t)m.xs_stride);
@@ -269,6 +273,7 @@ fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* id
   a.d = s.d;
   if (m.gram && s.dk != U8L2 && s.Q > 64) {
     a.gram = reinterpret_cast<float*>(at(ws, m.gram));
+    a.norm = reinterpret_cast<const float*>(at(ws, m.norm));
     grid = grid < kGramSlots ? grid : kGramSlots;
     if (m.xsp) a.split = GramSplit{reinterpret_cast<const uint8_t*>(at(ws, m.xsp)), m.xsp_stride};
   }
@@ -288,7 +293,10 @@ fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* id
   return FG_OK;
 }
 
+// Per-build preparation of the harvest's inputs beyond the rows: the row
+// norms of the Gram prune, then the narrow copy of a screened harvest.
 fg_status screen_launch(const Shape& s, const fg_params* P, void* ws, const WsMap& m, hipStream_t st) {
+  if (m.norm && s.dk != U8L2) FG_HIP(row_sq_norms(s, reinterpret_cast<float*>(at(ws, m.norm)), st));
   if (!P->screen) return FG_OK;
   FG_HIP(make_screen(s, copy_kind(P->screen), m.xs ? reinterpret_cast<uint8_t*>(at(ws, m.xs)) : nullptr,
                      reinterpret_cast<float*>(at(ws, m.xs_err)), reinterpret_cast<float*>(at(ws, m.xs_norm)),
@@ -417,6 +425,7 @@ fg_status finalize_launch(const Shape& s, const uint32_t* rows, const uint32_t* 
   f.counters = ctl->fin;
   f.d = s.d;
   f.gram = (m.gram && s.dk != U8L2 && s.Q > 64) ? reinterpret_cast<float*>(at(ws, m.gram)) : nullptr;
+  f.norm = f.gram ? reinterpret_cast<const float*>(at(ws, m.norm)) : nullptr;
   if (f.gram && m.xsp) f.split = GramSplit{reinterpret_cast<const uint8_t*>(at(ws, m.xsp)), m.xsp_stride};
   f.status = &ctl->status;
   f.big = reinterpret_cast<uint32_t*>(at(ws, m.big));

@@ -131,6 +131,9 @@ struct BeamArgs {
   float* gram;
   // the Gram tiles from the bfloat16 split of the rows (see GramSplit)
   GramSplit split;
+  // |x_i|^2 of every row (any float32 summation order): the Gram prune's
+  // diagonal (NULL: no Gram prune)
+  const float* norm;
 };
 
 constexpr int kGramMax = 1024;   // candidates the Gram-tile prune takes
@@ -419,8 +422,9 @@ typedef float gram_f32x16 __attribute__((ext_vector_type(16)));
 // Row of the 32x32 accumulator held in register r of lane l.
 __device__ __forceinline__ int gram_acc_row(int r, int lane) { return (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3); }
 
-// G[i * kGramMax + j] = <c_i, c_j> for j >= i, candidates c_i = row of sk[i].
-// Lanes l and l+32 read chunks c and c+1 of the same row: the four elements
+// G[i * kGramMax + j] = <c_i, c_j> for j > i, candidates c_i = row of sk[i],
+// one 32-row block-row at a time.  Lanes l and l+32 read chunks c and c+1 of
+// the same row: the four elements
 // of each 16-byte chunk are four k-steps of the 32x32x2 product.  Rows are
 // taken in steps of eight chunks (one 128-byte line per row), double-
 // buffered: a step's four loads per operand are issued together, one step
@@ -479,11 +483,13 @@ __device__ __forceinline__ void gram_tile_acc(gram_f32x16& acc, const uint8_t* p
   }
 }
 
-__device__ __forceinline__ void gram_tiles(const RowSet& X, const uint64_t* sk, int mc, float* G) {
+// Block-row I of G: G[i * kGramMax + j] = <c_i, c_j> for i in block I and
+// j > i (the tiles (I, J), J >= I).
+__device__ __forceinline__ void gram_row_block(const RowSet& X, const uint64_t* sk, int mc, float* G, int I) {
   const int lane = lane_id();
   const int nb = (mc + 31) / 32;
   const int h = lane >> 5;
-  for (int I = 0; I < nb; I++) {
+  {
     const int ra = 32 * I + (lane & 31);
     const uint8_t* pa = X.x + (size_t)key_id(sk[ra < mc ? ra : 0]) * X.stride + 16 * h;
     for (int J = I; J < nb; J++) {
@@ -497,7 +503,7 @@ __device__ __forceinline__ void gram_tiles(const RowSet& X, const uint64_t* sk, 
       for (int r = 0; r < 16; r++) {
         const int i = 32 * I + gram_acc_row(r, lane);
         const int j = 32 * J + (lane & 31);
-        if (i < mc && j < mc && j >= i) G[i * kGramMax + j] = acc[r];
+        if (i < mc && j < mc && j > i) G[i * kGramMax + j] = acc[r];
       }
     }
   }
@@ -512,18 +518,19 @@ __device__ __forceinline__ void gram_mfma_split(gram_f32x16& acc, const gram_bf1
   acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
 }
 
-// gram_tiles from the split rows: <a,c> ~ <ah,ch> + <ah,cl> + <al,ch> (the
+// gram_row_block from the split rows: <a,c> ~ <ah,ch> + <ah,cl> + <al,ch> (the
 // dropped <al,cl> and the residuals e are covered by the margin).  A
 // 16-element step is one 32x32x16 product per term: lane l reads the eight
 // k-values at bytes 16 (l >> 5) of the step's hi and lo halves, so lanes l
 // and l + 32 together take the step's whole 64 bytes of the row.  Same
-// accumulator layout and stores as gram_tiles.
-__device__ __forceinline__ void gram_tiles_split(const GramSplit& gs, const uint64_t* sk, int mc, float* G) {
+// accumulator layout and stores as gram_row_block.
+__device__ __forceinline__ void gram_row_block_split(const GramSplit& gs, const uint64_t* sk, int mc, float* G,
+                                                     int I) {
   const int lane = lane_id();
   const int nb = (mc + 31) / 32;
   const int K = (int)(gs.stride / 64);
   const uint8_t* base = gs.p + 16 * (size_t)(lane >> 5);
-  for (int I = 0; I < nb; I++) {
+  {
     const int ra = 32 * I + (lane & 31);
     const size_t oa = (size_t)key_id(sk[ra < mc ? ra : 0]) * gs.stride;
     for (int J = I; J < nb; J++) {
@@ -562,7 +569,7 @@ __device__ __forceinline__ void gram_tiles_split(const GramSplit& gs, const uint
       for (int r = 0; r < 16; r++) {
         const int i = 32 * I + gram_acc_row(r, lane);
         const int j = 32 * J + (lane & 31);
-        if (i < mc && j < mc && j >= i) G[i * kGramMax + j] = acc[r];
+        if (i < mc && j < mc && j > i) G[i * kGramMax + j] = acc[r];
       }
     }
   }
@@ -646,12 +653,17 @@ __device__ __forceinline__ float group_dist_stream(const uint8_t* ra, const uint
 }
 
 // The greedy prune of prune_wave, its pair tests decided from the Gram
-// matrix (gram_tiles, then a fence) where the margin allows.  G is this
-// wave's kGramMax^2 scratch; *rc counts the exact recomputations.
+// matrix where the margin allows.  A block-row of G is computed (then
+// fenced) when the greedy first keeps a candidate of that block: with
+// candidates sorted by distance and at most R kept, later blocks often are
+// never needed.  The diagonal comes from norm (|x|^2 of every row, any
+// float32 order: within the same margin).  G is this wave's kGramMax^2
+// scratch; *rc counts the exact recomputations.
 template <int DK, int L, int NCH>
-__device__ int prune_gram(const RowSet& X, int d, bool split, float alpha, int R, const uint64_t* sk, int mc,
-                          const float* G, uint32_t* alive, uint32_t* cid, uint64_t* ckey, uint32_t* out,
-                          unsigned long long* pe, unsigned long long* rc) {
+__device__ int prune_gram(const RowSet& X, int d, const GramSplit& split, const float* norm, float alpha, int R,
+                          const uint64_t* sk, int mc, float* G, uint32_t* alive, uint32_t* cid, uint64_t* ckey,
+                          uint32_t* out, unsigned long long* pe, unsigned long long* rc) {
+  uint32_t rows_done = 0;  // block-rows of G computed so far (at most 32)
   const int lane = lane_id();
   const int g = lane % L;
   for (int w = lane; w < (mc + 31) / 32; w += 64) {
@@ -678,7 +690,18 @@ __device__ int prune_gram(const RowSet& X, int d, bool split, float alpha, int R
     if (lane == 0) out[kept] = kid;
     kept++;
     if (kept == R) break;
-    const float gaa = G[i * kGramMax + i];
+    if (!((rows_done >> (i >> 5)) & 1u)) {
+      if (split.p)
+        gram_row_block_split(split, sk, mc, G, i >> 5);
+      else
+        gram_row_block(X, sk, mc, G, i >> 5);
+      // the tiles were written by other lanes, and this slot's scratch may
+      // sit in the vector L1 from an earlier search: make the stores
+      // visible and drop stale lines before reading them back
+      __threadfence();
+      rows_done |= 1u << (i >> 5);
+    }
+    const float gaa = norm[kid];
     const uint8_t* krow = X.x + (size_t)kid * X.stride;
     for (int base = i + 1; base < mc; base += 64) {
       int j = base + lane;
@@ -691,9 +714,9 @@ __device__ int prune_gram(const RowSet& X, int d, bool split, float alpha, int R
       float dpc = 0.0f;
       if (live) {
         dpc = hi_to_float<DK>(key_hi(sk[j]));
-        const float gcc = G[j * kGramMax + j], gac = G[i * kGramMax + j];
+        const float gcc = norm[key_id(sk[j])], gac = G[i * kGramMax + j];
         const float dt = DK == F32L2 ? (gaa + gcc) - 2.0f * gac : 1.0f - gac;
-        const float eps = gram_eps<DK>(dt, gaa, gcc, d, split);
+        const float eps = gram_eps<DK>(dt, gaa, gcc, d, split.p != nullptr);
         // bounds on fl(alpha * exact), widened for their own roundings
         const float up = alpha * (dt + eps), lo = alpha * (dt - eps);
         if (up + fabsf(up) * u8 < dpc) kill = true;
@@ -956,20 +979,11 @@ k_beam(BeamArgs A) {
         FG_TICK(5);
         bool gram = false;
         if constexpr (DK != U8L2 && NCH >= 16)
-          gram = A.gram != nullptr && mc <= kGramMax && wslot < kGramSlots;
+          gram = A.gram != nullptr && A.norm != nullptr && mc <= kGramMax && wslot < kGramSlots;
         if (gram) {
           float* G = A.gram + (size_t)wslot * kGramMax * kGramMax;
-          if (A.split.p)
-            gram_tiles_split(A.split, sk, mc, G);
-          else
-            gram_tiles(X, sk, mc, G);
-          // the tiles were written by other lanes, and this slot's scratch
-          // may sit in the vector L1 from an earlier search: make the
-          // stores visible and drop stale lines before reading them back
-          __threadfence();
-          FG_TICK(8);
-          kept = prune_gram<DK, L, NCH>(X, A.d, A.split.p != nullptr, A.alpha, A.R, sk, mc, G, S.alive, S.cid,
-                                        S.ckey, out, &my_pe, &my_rc);
+          kept = prune_gram<DK, L, NCH>(X, A.d, A.split, A.norm, A.alpha, A.R, sk, mc, G, S.alive, S.cid, S.ckey,
+                                        out, &my_pe, &my_rc);
         } else
           kept = prune_wave<DK, L, NCH>(X, A.alpha, A.R, sk, mc, S.alive, S.cid, S.ckey, out, &my_pe);
         FG_TICK(4);

@@ -68,16 +68,12 @@ __device__ void fin_point(const FinalizeArgs& A, int64_t p, uint32_t* cb, uint64
   int kept;
   if (m > A.R || A.reprune_all) {
     bool gram = false;
-    if constexpr (DK != U8L2 && NCH >= 16) gram = A.gram != nullptr && m <= kGramMax && blockIdx.x < kGramSlots;
+    if constexpr (DK != U8L2 && NCH >= 16)
+      gram = A.gram != nullptr && A.norm != nullptr && m <= kGramMax && blockIdx.x < kGramSlots;
     if (gram) {  // matrix-core pair distances with exact rechecks (see prune_gram)
       float* G = A.gram + (size_t)blockIdx.x * kGramMax * kGramMax;
-      if (A.split.p)
-        gram_tiles_split(A.split, sk, m, G);
-      else
-        gram_tiles(A.X, sk, m, G);
-      __threadfence();
-      kept = prune_gram<DK, L, NCH>(A.X, A.d, A.split.p != nullptr, A.alpha, A.R, sk, m, G, alive, cid, ckey, out,
-                                    &pe, &rcheck);
+      kept = prune_gram<DK, L, NCH>(A.X, A.d, A.split, A.norm, A.alpha, A.R, sk, m, G, alive, cid, ckey, out, &pe,
+                                    &rcheck);
     } else {
       kept = prune_wave<DK, L, NCH>(A.X, A.alpha, A.R, sk, m, alive, cid, ckey, out, &pe);
     }

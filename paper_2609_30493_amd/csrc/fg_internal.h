@@ -49,6 +49,8 @@ int64_t screen_stride(int d, int screen);
 // xs may be NULL (no plain copy); sp (bfloat16 only, may be NULL) receives
 // the interleaved hi/lo split, rows split_stride(d) bytes apart.
 int64_t split_stride(int d);
+// |x_i|^2 of every float32 row (fg_sat.hip).
+hipError_t row_sq_norms(const Shape& s, float* out, hipStream_t st);
 hipError_t make_screen(const Shape& s, int screen, uint8_t* xs, float* err, float* norm, float* sinv,
                        hipStream_t st, uint8_t* sp = nullptr);
 
@@ -123,6 +125,7 @@ struct FinalizeArgs {
   int d;
   float* gram;     // float32 rows longer than 256 elements: Gram scratch per block (or NULL)
   GramSplit split; // the Gram tiles from the bfloat16 split (p NULL: from the rows)
+  const float* norm;  // |x_i|^2 per row for the Gram prune (NULL: no Gram prune)
 };
 struct FinalizeBig {
   KSeg* segs;

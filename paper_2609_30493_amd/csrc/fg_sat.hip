@@ -893,6 +893,11 @@ __global__ void __launch_bounds__(256) k_sat_norms(const uint8_t* x, int64_t str
 }
 }  // namespace
 
+hipError_t row_sq_norms(const Shape& s, float* out, hipStream_t st) {
+  k_sat_norms<<<(unsigned)blocks_for(s.n, 4), 256, 0, st>>>(s.x, s.stride, s.n, s.Q, out);
+  return hipGetLastError();
+}
+
 size_t sat_workspace_bytes(int64_t n, uint32_t T, SatWs* w) {
   size_t o = 0;
   auto take = [&](size_t bytes) {

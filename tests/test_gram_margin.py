@@ -103,8 +103,12 @@ def test_gram_margin_bounds_exact_distance(fgo, metric, split, d):
     for a, c in pairs(metric, rng, d):
         D = fgo.Data(np.stack([a, c]), metric=metric)
         exact = float(fgo.dist(D, 0, 1))
-        for mode in modes:
-            gaa, gcc, gac = (gram_entry(u, v, split, mode) for u, v in ((a, a), (c, c), (a, c)))
+        for mode in modes + (("norms",) if split else ()):
+            if mode == "norms":  # the kernels' combination: split <a,c>, float32 |a|^2, |c|^2
+                gaa, gcc = gram_entry(a, a, False, "seq"), gram_entry(c, c, False, "pair")
+                gac = gram_entry(a, c, True, "steps")
+            else:
+                gaa, gcc, gac = (gram_entry(u, v, split, mode) for u, v in ((a, a), (c, c), (a, c)))
             if metric == "l2":
                 dt = float(np.float32(np.float32(gaa + gcc) - np.float32(np.float32(2) * gac)))
             else:
