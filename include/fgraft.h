@@ -171,8 +171,11 @@ typedef struct {
 } fg_timings;
 
 /* Bytes of device scratch needed by every entry point below for this data
- * shape and these parameters (one workspace serves all of them; a screened
- * harvest adds the narrow copy and three floats per row). */
+ * shape and these parameters (one workspace serves all of them).  FG_F32
+ * rows of 257..1024 elements add 8 GiB of Gram-prune scratch (2048 wave
+ * slots of 1024 x 1024 floats) and a float per row; a screened harvest adds
+ * the narrow copy and three floats per row, the split tiles 4d bytes per
+ * row. */
 size_t fg_workspace_size(const fg_data* data, const fg_params* params);
 
 /* Keyed roots (Prop. 1, "keyed randomness"): root of tree t is the first
