@@ -228,6 +228,7 @@ struct BatchInfo {
   const uint32_t* inst_roots;
   const int* inst_ef;
   int ef_max;
+  const int* inst_q;  // 16-byte chunks of each instance's own rows
 };
 
 fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* ids,
@@ -281,6 +282,7 @@ fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* id
     a.inst_of = bi->inst_of;
     a.inst_roots = bi->inst_roots;
     a.inst_ef = bi->inst_ef;
+    a.inst_q = bi->inst_q;
   }
   if (screen) {
     a.xs = reinterpret_cast<const uint8_t*>(at(ws, m.xs));
@@ -396,7 +398,8 @@ fg_status scaffold_csr_launch(int64_t n, uint32_t T, const uint32_t* tparent, ui
 }
 
 fg_status finalize_launch(const Shape& s, const uint32_t* rows, const uint32_t* cnt, const fg_params* P,
-                          uint32_t* g_nbrs, uint32_t* g_cnt, void* ws, const WsMap& m, hipStream_t st) {
+                          uint32_t* g_nbrs, uint32_t* g_cnt, void* ws, const WsMap& m, hipStream_t st,
+                          const BatchInfo* bi = nullptr) {
   const int64_t n = s.n;
   const int R = (int)P->R;
   uint32_t* deg = reinterpret_cast<uint32_t*>(at(ws, m.deg));
@@ -426,6 +429,10 @@ fg_status finalize_launch(const Shape& s, const uint32_t* rows, const uint32_t* 
   f.d = s.d;
   f.gram = (m.gram && s.dk != U8L2 && s.Q > 64) ? reinterpret_cast<float*>(at(ws, m.gram)) : nullptr;
   f.norm = f.gram ? reinterpret_cast<const float*>(at(ws, m.norm)) : nullptr;
+  if (bi) {
+    f.inst_of = bi->inst_of;
+    f.inst_q = bi->inst_q;
+  }
   if (f.gram && m.xsp) f.split = GramSplit{reinterpret_cast<const uint8_t*>(at(ws, m.xsp)), m.xsp_stride};
   f.status = &ctl->status;
   f.big = reinterpret_cast<uint32_t*>(at(ws, m.big));
@@ -1052,7 +1059,7 @@ struct BatchPlan {
   int ef_max = 0;
   std::vector<int64_t> off;
   WsMap m;
-  size_t x_at = 0, inst_at = 0, roots_at = 0, ef_at = 0, nbrs_at = 0, gcnt_at = 0;
+  size_t x_at = 0, inst_at = 0, roots_at = 0, ef_at = 0, q_at = 0, nbrs_at = 0, gcnt_at = 0;
   size_t total = 0;
 };
 
@@ -1103,6 +1110,7 @@ bool plan_batch(const fg_data* const* data, const fg_params* const* params, uint
   bp->inst_at = take(N * 2);
   bp->roots_at = take((uint64_t)count * T * 4);
   bp->ef_at = take((uint64_t)count * 4);
+  bp->q_at = take((uint64_t)count * 4);
   bp->nbrs_at = take(N * R * 4);
   bp->gcnt_at = take(N * 4);
   bp->total = o;
@@ -1142,6 +1150,7 @@ fg_status fg_build_graph_batched(const fg_data* const* data, const fg_params* co
   uint16_t* inst_of = reinterpret_cast<uint16_t*>(at(ws_dev, bp.inst_at));
   uint32_t* inst_roots = reinterpret_cast<uint32_t*>(at(ws_dev, bp.roots_at));
   int* inst_ef = reinterpret_cast<int*>(at(ws_dev, bp.ef_at));
+  int* inst_q = reinterpret_cast<int*>(at(ws_dev, bp.q_at));
   uint32_t* gnbrs = reinterpret_cast<uint32_t*>(at(ws_dev, bp.nbrs_at));
   uint32_t* gcnt = reinterpret_cast<uint32_t*>(at(ws_dev, bp.gcnt_at));
   uint32_t* tparent = reinterpret_cast<uint32_t*>(at(ws_dev, m.tparent));
@@ -1156,7 +1165,7 @@ fg_status fg_build_graph_batched(const fg_data* const* data, const fg_params* co
   FG_HIP(fill_u32(reinterpret_cast<uint32_t*>(X), 0, N * bp.stride / 4, st));
   std::vector<uint16_t> hinst((size_t)N, 0xFFFFu);
   std::vector<uint32_t> hroots_all((size_t)count * T), hroots_local((size_t)count * T);
-  std::vector<int> hef(count);
+  std::vector<int> hef(count), hq(count);
   for (uint32_t i = 0; i < count; i++) {
     const fg_data* di = data[i];
     const int64_t esz = di->dtype == FG_U8 ? 1 : 4;
@@ -1168,10 +1177,12 @@ fg_status fg_build_graph_batched(const fg_data* const* data, const fg_params* co
     for (uint32_t t = 0; t < T; t++)
       hroots_all[(size_t)i * T + t] = hroots_local[(size_t)i * T + t] + (uint32_t)bp.off[i];
     hef[i] = (int)params[i]->ef_h;
+    hq[i] = bp.s.dk == U8L2 ? data[i]->d / 16 : data[i]->d / 4;
   }
   FG_HIP(hipMemcpyAsync(inst_of, hinst.data(), hinst.size() * 2, hipMemcpyHostToDevice, st));
   FG_HIP(hipMemcpyAsync(inst_roots, hroots_all.data(), hroots_all.size() * 4, hipMemcpyHostToDevice, st));
   FG_HIP(hipMemcpyAsync(inst_ef, hef.data(), hef.size() * 4, hipMemcpyHostToDevice, st));
+  FG_HIP(hipMemcpyAsync(inst_q, hq.data(), hq.size() * 4, hipMemcpyHostToDevice, st));
   fg_status r = reset_ctl(ws_dev, m, st);
   if (r) return r;
   FG_HIP(hipStreamSynchronize(st));  // the host tables above must outlive their copies
@@ -1189,7 +1200,7 @@ fg_status fg_build_graph_batched(const fg_data* const* data, const fg_params* co
   if (r) return r;
 
   // Blocks.
-  const BatchInfo bi{inst_of, inst_roots, inst_ef, bp.ef_max};
+  const BatchInfo bi{inst_of, inst_roots, inst_ef, bp.ef_max, inst_q};
   auto init_rows = [&](hipStream_t s_) -> fg_status {
     FG_HIP(fill_u32(rows, FG_NONE, N * (int64_t)R, s_));
     FG_HIP(fill_u32(cnt, 0, N, s_));
@@ -1255,7 +1266,7 @@ fg_status fg_build_graph_batched(const fg_data* const* data, const fg_params* co
   }
 
   // Finalize over the shared id space, then each instance in its own ids.
-  r = finalize_launch(bp.s, rows, cnt, &bp.P, gnbrs, gcnt, ws_dev, m, st);
+  r = finalize_launch(bp.s, rows, cnt, &bp.P, gnbrs, gcnt, ws_dev, m, st, &bi);
   if (r) return r;
   for (uint32_t i = 0; i < count; i++) {
     FG_HIP(localize_graph(gnbrs, gcnt, tparent, data[i]->n, (int)R, bp.off[i], outs[i]->nbrs_dev, outs[i]->cnt_dev,

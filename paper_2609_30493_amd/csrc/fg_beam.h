@@ -126,6 +126,7 @@ struct BeamArgs {
   const uint16_t* inst_of;
   const uint32_t* inst_roots;
   const int* inst_ef;
+  const int* inst_q;  // 16-byte chunks of instance i's own rows (the rest of a row is zero)
   // float32 rows of more than 64 chunks: per wave slot a kGramMax^2 float
   // scratch for the candidates' Gram matrix (NULL: exact prune only)
   float* gram;
@@ -762,7 +763,7 @@ k_beam(BeamArgs A) {
   constexpr int HCAP = HSLOTS / 2 - 64;  // load <= 1/2; checked after every 64 insertions
   // rows in flight per lane group, sized to the register budget above
   constexpr int kRB = (NCH >= 16) ? 1 : (NCH == 1 ? (HSLOTS == 1024 ? 8 : 12) : 16 / NCH);
-  const RowSet X{A.x, A.stride, A.Q};
+  RowSet X{A.x, A.stride, A.Q};
 
   unsigned long long my_evals = 0, my_exp = 0, my_pe = 0, my_spilled = 0, my_rej = 0, my_rc = 0;
 #ifdef FG_PROFILE
@@ -785,11 +786,15 @@ k_beam(BeamArgs A) {
         if (inst == 0xFFFFu) continue;  // an unused id between instances
         ef = A.inst_ef[inst];
         roots = A.inst_roots + (size_t)inst * A.T;
+        // a query and its candidates share the instance: its zero chunks
+        // add exactly nothing, so they are not read (rows of up to 64
+        // chunks; longer rows keep the register budget of the Gram prune)
+        if constexpr (NCH <= 4) X.Q = A.inst_q[inst];
       }
     }
     const uint8_t* qrow = SEARCH ? A.queries + (size_t)item * A.qstride : A.x + (size_t)p * A.stride;
     Chunks<L, NCH> qc;
-    load_chunks<L, NCH>(qc, qrow, A.Q, g);
+    load_chunks<L, NCH>(qc, qrow, X.Q, g);
     uint32_t qn = 0;
     if constexpr (DK == U8L2) qn = group_sum_u32<L>(u8_selfdot<L, NCH>(qc));
     float qnorm = 0.0f;  // |p| for the cosine screen margin

@@ -23,6 +23,8 @@ __device__ void fin_point(const FinalizeArgs& A, int64_t p, uint32_t* cb, uint64
                           unsigned long long& rcheck) {
   const int lane = lane_id();
   const int g = lane % L;
+  RowSet X = A.X;  // a batched point and its candidates share the instance's own length
+  if (A.inst_q) X.Q = A.inst_q[A.inst_of[p]];
   uint32_t* out = A.g_nbrs + p * A.R;
   const int c = (int)min(A.cnt[p], (uint32_t)A.R);  // counts above R are not trusted
   const uint64_t r0 = A.revoff[p];
@@ -52,12 +54,12 @@ __device__ void fin_point(const FinalizeArgs& A, int64_t p, uint32_t* cb, uint64
     wave_sync();
   }
   Chunks<L, NCH> qc;
-  load_chunks<L, NCH>(qc, A.X.x + (size_t)p * A.X.stride, A.X.Q, g);
+  load_chunks<L, NCH>(qc, X.x + (size_t)p * X.stride, X.Q, g);
   uint32_t qn = 0;
   if constexpr (DK == U8L2) qn = group_sum_u32<L>(u8_selfdot<L, NCH>(qc));
   for (int base = 0; base < m; base += 64) {
     int cnt = m - base < 64 ? m - base : 64;
-    batch_dists_rs<DK, L, NCH>(A.X, qc, qn, cb + base, cnt, sk + base);
+    batch_dists_rs<DK, L, NCH>(X, qc, qn, cb + base, cnt, sk + base);
   }
   ev += (unsigned long long)m;
   int Mk = 64;
@@ -72,10 +74,10 @@ __device__ void fin_point(const FinalizeArgs& A, int64_t p, uint32_t* cb, uint64
       gram = A.gram != nullptr && A.norm != nullptr && m <= kGramMax && blockIdx.x < kGramSlots;
     if (gram) {  // matrix-core pair distances with exact rechecks (see prune_gram)
       float* G = A.gram + (size_t)blockIdx.x * kGramMax * kGramMax;
-      kept = prune_gram<DK, L, NCH>(A.X, A.d, A.split, A.norm, A.alpha, A.R, sk, m, G, alive, cid, ckey, out, &pe,
+      kept = prune_gram<DK, L, NCH>(X, A.d, A.split, A.norm, A.alpha, A.R, sk, m, G, alive, cid, ckey, out, &pe,
                                     &rcheck);
     } else {
-      kept = prune_wave<DK, L, NCH>(A.X, A.alpha, A.R, sk, m, alive, cid, ckey, out, &pe);
+      kept = prune_wave<DK, L, NCH>(X, A.alpha, A.R, sk, m, alive, cid, ckey, out, &pe);
     }
   } else {
     for (int i = lane; i < m; i += 64) out[i] = key_id(sk[i]);

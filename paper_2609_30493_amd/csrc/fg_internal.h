@@ -126,6 +126,10 @@ struct FinalizeArgs {
   float* gram;     // float32 rows longer than 256 elements: Gram scratch per block (or NULL)
   GramSplit split; // the Gram tiles from the bfloat16 split (p NULL: from the rows)
   const float* norm;  // |x_i|^2 per row for the Gram prune (NULL: no Gram prune)
+  // batched builds: each point's instance and the chunks of that instance's
+  // own rows (NULL: every row has X.Q chunks)
+  const uint16_t* inst_of;
+  const int* inst_q;
 };
 struct FinalizeBig {
   KSeg* segs;
