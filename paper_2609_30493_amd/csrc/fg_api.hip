@@ -1193,7 +1193,8 @@ fg_status fg_build_graph_batched(const fg_data* const* data, const fg_params* co
     std::vector<SatInstance> si(count);
     for (uint32_t i = 0; i < count; i++) si[i] = SatInstance{bp.off[i], data[i]->n, &hroots_local[(size_t)i * T]};
     int status = 0;
-    FG_HIP(sat_build_multi(bp.s, T, si, tparent, at(ws_dev, m.sat), m.satw, st, &sat_evals, &status));
+    FG_HIP(sat_build_multi(bp.s, T, si, tparent, at(ws_dev, m.sat), m.satw, st, &sat_evals, &status, inst_of,
+                           inst_q));
     if (status) return status_error(status);
   }
   r = scaffold_csr_launch(N, T, tparent, off[0], ids[0], ws_dev, m, st);

@@ -24,7 +24,8 @@ __device__ void fin_point(const FinalizeArgs& A, int64_t p, uint32_t* cb, uint64
   const int lane = lane_id();
   const int g = lane % L;
   RowSet X = A.X;  // a batched point and its candidates share the instance's own length
-  if (A.inst_q) X.Q = A.inst_q[A.inst_of[p]];
+  if constexpr (DK != U8L2 && NCH <= 4)  // (uint8 rows: the register budget of five waves per SIMD)
+    if (A.inst_q) X.Q = A.inst_q[A.inst_of[p]];
   uint32_t* out = A.g_nbrs + p * A.R;
   const int c = (int)min(A.cnt[p], (uint32_t)A.R);  // counts above R are not trusted
   const uint64_t r0 = A.revoff[p];

@@ -55,6 +55,10 @@ struct SatArgs {
   // assignment (NULL: exact streaming assignment only)
   const float* norm;
   int d;
+  // batched builds: each id's instance and the 16-byte chunks of that
+  // instance's own rows (NULL: every row has X.Q chunks)
+  const uint16_t* inst_of;
+  const int* inst_q;
 };
 
 struct SatWs {
@@ -76,8 +80,11 @@ struct SatInstance {
   int64_t off, n;
   const uint32_t* roots;
 };
+// inst_of / inst_q (optional, device): each id's instance and the chunks of
+// its own rows, so that bags read only those.
 hipError_t sat_build_multi(const Shape& s, uint32_t T, const std::vector<SatInstance>& inst, uint32_t* parent,
-                           char* ws, const SatWs& w, hipStream_t st, unsigned long long* evals, int* status);
+                           char* ws, const SatWs& w, hipStream_t st, unsigned long long* evals, int* status,
+                           const uint16_t* inst_of = nullptr, const int* inst_q = nullptr);
 // Directed edges of the T trees in both directions, grouped by source row
 // (unsorted, with repeats) into tmp_ids at offsets off_tmp.
 hipError_t tree_edges_csr(int64_t n, uint32_t T, const uint32_t* parent, uint32_t* deg,

@@ -30,6 +30,17 @@ namespace {
 
 constexpr int kTile = 256;  // positions per wave in the large-bag passes
 
+// The rows a bag centred at `center` compares: in a batched build only the
+// chunks of the instance's own rows (the padding is zero and adds exactly
+// nothing).  Rows of more than 64 chunks keep the full length.
+template <int NCH>
+__device__ __forceinline__ RowSet sat_rows(const SatArgs& A, uint32_t center) {
+  RowSet X = A.X;
+  if constexpr (NCH <= 4)
+    if (A.inst_q) X.Q = A.inst_q[A.inst_of[center]];
+  return X;
+}
+
 // ---------------------------------------------------------------- large bags
 // Keys (d(v, center), v) of every position of the large bags.
 template <int DK, int L, int NCH>
@@ -40,7 +51,8 @@ __global__ void __launch_bounds__(64) k_sat_keys(SatArgs A) {
   const SatTile tl = A.tiles[blockIdx.x];
   const SatSeg sg = A.segs[tl.seg];
   Chunks<L, NCH> ac;
-  load_chunks<L, NCH>(ac, A.X.x + (size_t)sg.center * A.X.stride, A.X.Q, g);
+  const RowSet X = sat_rows<NCH>(A, sg.center);
+  load_chunks<L, NCH>(ac, X.x + (size_t)sg.center * X.stride, X.Q, g);
   uint32_t an = 0;
   if constexpr (DK == U8L2) an = group_sum_u32<L>(u8_selfdot<L, NCH>(ac));
   const uint32_t lo = tl.off, hi = min(sg.len, tl.off + kTile);
@@ -48,7 +60,7 @@ __global__ void __launch_bounds__(64) k_sat_keys(SatArgs A) {
     int cnt = (int)min(64u, hi - base);
     if (lane < cnt) cid[lane] = A.perm[sg.start + base + lane];
     wave_sync();
-    batch_dists_rs<DK, L, NCH>(A.X, ac, an, cid, cnt, ckey);
+    batch_dists_rs<DK, L, NCH>(X, ac, an, cid, cnt, ckey);
     if (lane < cnt) {
       A.key[sg.start + base + lane] = ckey[lane];
       A.flag[sg.start + base + lane] = 0;
@@ -156,7 +168,7 @@ __global__ void __launch_bounds__(64) k_sat_resolve(SatArgs A) {
   }
   wave_sync();
   unsigned long long pe = 0;
-  int kept = prune_wave<DK, L, NCH>(A.X, 1.0f, 65, sk, k, alive, cid, ckey, acc, &pe);
+  int kept = prune_wave<DK, L, NCH>(sat_rows<NCH>(A, sg.center), 1.0f, 65, sk, k, alive, cid, ckey, acc, &pe);
   // prune_wave left alive bits on exactly the accepted candidates.  Mark
   // the chunk's positions: they are the first k undecided ones from the old
   // pos, so walk them again in the same order.
@@ -322,12 +334,13 @@ __global__ void __launch_bounds__(64) k_sat_filter(SatArgs A) {
     for (uint32_t kb = sg.nN_prev; kb < sg.nN && cnt > 0; kb++) {
       uint32_t b = A.nl[sg.start + kb];
       Chunks<L, NCH> bc;
-      load_chunks<L, NCH>(bc, A.X.x + (size_t)b * A.X.stride, A.X.Q, g);
+      const RowSet X = sat_rows<NCH>(A, sg.center);
+      load_chunks<L, NCH>(bc, X.x + (size_t)b * X.stride, X.Q, g);
       uint32_t bn = 0;
       if constexpr (DK == U8L2) bn = group_sum_u32<L>(u8_selfdot<L, NCH>(bc));
       if (lane < cnt) cid[lane] = key_id(cdk[lane]);
       wave_sync();
-      batch_dists_rs<DK, L, NCH>(A.X, bc, bn, cid, cnt, ckey);
+      batch_dists_rs<DK, L, NCH>(X, bc, bn, cid, cnt, ckey);
       ev += (unsigned long long)cnt;
       bool keep = false;
       uint32_t mypos = 0;
@@ -515,7 +528,7 @@ __global__ void __launch_bounds__(64) k_sat_assign(SatArgs A) {
     if (gram)
       argmin_gram<DK, L, NCH>(A.X, A.d, A.norm, cand, cnt, A.nl + sg.start, (int)sg.nN, own, &ev, gbest, gqi, gqj);
     else
-      argmin_wave<DK, L, NCH>(A.X, cand, cnt, A.nl + sg.start, (int)sg.nN, own, &ev);
+      argmin_wave<DK, L, NCH>(sat_rows<NCH>(A, sg.center), cand, cnt, A.nl + sg.start, (int)sg.nN, own, &ev);
     if (lane < cnt) A.owner[sg.start + cpos[lane]] = own[lane];
     wave_sync();
   }
@@ -683,14 +696,15 @@ __global__ void __launch_bounds__(64) k_sat_small(SatArgs A, uint32_t nsmall) {
       wave_sync();
       // keys (d(v, a), v)
       Chunks<L, NCH> ac;
-      load_chunks<L, NCH>(ac, A.X.x + (size_t)a * A.X.stride, A.X.Q, g);
+      const RowSet X = sat_rows<NCH>(A, sg.center);
+      load_chunks<L, NCH>(ac, X.x + (size_t)a * X.stride, X.Q, g);
       uint32_t an = 0;
       if constexpr (DK == U8L2) an = group_sum_u32<L>(u8_selfdot<L, NCH>(ac));
       for (int base = 0; base < m; base += 64) {
         int cnt = min(64, m - base);
         if (lane < cnt) cid[lane] = A.perm[s + base + lane];
         wave_sync();
-        batch_dists_rs<DK, L, NCH>(A.X, ac, an, cid, cnt, sk + base);
+        batch_dists_rs<DK, L, NCH>(X, ac, an, cid, cnt, sk + base);
       }
       ev_keys += (unsigned long long)m;
       int M = 64;
@@ -699,7 +713,7 @@ __global__ void __launch_bounds__(64) k_sat_small(SatArgs A, uint32_t nsmall) {
       wave_sync();
       wave_sort_lds<uint64_t>(sk, M);
       // acceptance = prune with alpha 1, unbounded degree
-      const int nn = prune_wave<DK, L, NCH>(A.X, 1.0f, m + 1, sk, m, alive, cid, ckey, nb, &ev_acc);
+      const int nn = prune_wave<DK, L, NCH>(X, 1.0f, m + 1, sk, m, alive, cid, ckey, nb, &ev_acc);
       wave_sync();
       // rejected candidates: closest neighbour
       int nrej = 0;
@@ -716,7 +730,7 @@ __global__ void __launch_bounds__(64) k_sat_small(SatArgs A, uint32_t nsmall) {
           if (gram)  // best in ckey, the queue in cc (free until the counts below)
             argmin_gram<DK, L, NCH>(A.X, A.d, A.norm, cid, cnt, nb, nn, own + nrej, &ev_asg, ckey, cc, cc + 64);
           else
-            argmin_wave<DK, L, NCH>(A.X, cid, cnt, nb, nn, own + nrej, &ev_asg);
+            argmin_wave<DK, L, NCH>(X, cid, cnt, nb, nn, own + nrej, &ev_asg);
           if (lane < cnt) A.stk_tmp[s + nrej + lane] = cid[lane];  // id of rejected #(nrej + lane)
           nrej += cnt;
         }
@@ -946,7 +960,7 @@ hipError_t sat_build(const Shape& s, const uint32_t* roots, uint32_t T, uint32_t
 
 hipError_t sat_build_multi(const Shape& s, uint32_t T, const std::vector<SatInstance>& inst, uint32_t* parent,
                            char* ws, const SatWs& w, hipStream_t st, unsigned long long* host_evals,
-                           int* host_status) {
+                           int* host_status, const uint16_t* inst_of, const int* inst_q) {
   KSet K;
   if (!pick_kset(s.dk, s.Q, &K)) return hipErrorInvalidValue;
   if (T > 64) return hipErrorInvalidValue;
@@ -980,6 +994,8 @@ hipError_t sat_build_multi(const Shape& s, uint32_t T, const std::vector<SatInst
   a.n_small = &ctl->n_small;
   a.status = &ctl->status;
   a.d = s.d;
+  a.inst_of = inst_of;
+  a.inst_q = inst_of ? inst_q : nullptr;
   hipError_t e;
 #define CK(x)                       \
   do {                              \
