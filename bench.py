@@ -383,8 +383,8 @@ def main():
                          "kernel of known size, to scale profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the harvest would shard).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the harvest would shard by points over replicated rows and substrate).", file=sys.stderr)
         sys.exit(2)
     if args.mode == "dsweep":
         return dsweep(args)

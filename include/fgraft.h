@@ -51,7 +51,7 @@ typedef enum {
   FG_ENOMEM = -2,        /* workspace too small */
   FG_EHIP = -3,          /* a HIP runtime call failed */
   FG_ECAPACITY = -4,     /* a device-side bounded buffer overflowed */
-  FG_EUNSUPPORTED = -5   /* shape this build has no kernel for */
+  FG_EUNSUPPORTED = -5   /* a shape the library has no kernel for */
 } fg_status;
 
 typedef enum { FG_F32 = 0, FG_U8 = 1 } fg_dtype;
