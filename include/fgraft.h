@@ -95,7 +95,8 @@ typedef struct {
  * symmetrised candidate set exceeds R; 1 re-prunes every row.
  * beam_table_slots is a tuning knob that never changes the graph: the size
  * of each harvest search's on-chip visited table, 1024, 2048 or 4096 (0 =
- * 2048 when ef_h <= 128, else 4096; ef_h > 128 always uses 4096; 1024
+ * 4096 for FG_F32 rows of more than 256 elements, else 2048 when
+ * ef_h <= 128 and 4096 otherwise; ef_h > 128 always uses 4096; 1024
  * applies to ef_h <= 64 with rows of at most 256 bytes, else 2048 is used).
  * Smaller tables let more searches run per compute unit.  A search whose
  * expanded set exceeds half the table size fails with FG_ECAPACITY.

@@ -94,10 +94,14 @@ uint32_t b_eff(const fg_params* p) { return p->B > 1 ? p->B : 1; }
 
 // Visited-table size for the harvest: the caller's choice, else 2048 slots
 // when ef_h <= 128 (more searches resident per compute unit; measured faster
-// on the 1M uint8 build) and 4096 otherwise.
-int table_request(const fg_params* p) {
+// on the 1M uint8 build) and 4096 otherwise.  Rows of more than 64 chunks
+// (nch 16) take 4096: their registers already hold residency at two searches
+// per SIMD, and the larger table keeps searches off the device bitset
+// (measured 6% faster on the 200,000 x 960 build).
+int table_request(const fg_params* p, int nch = 1) {
   if (p->beam_table_slots == 1024 || p->beam_table_slots == 2048 || p->beam_table_slots == 4096)
     return (int)p->beam_table_slots;
+  if (nch >= 16) return 4096;
   return p->ef_h <= 128 ? 2048 : 4096;
 }
 
@@ -241,7 +245,7 @@ fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* id
   FG_HIP(fill_u64(reinterpret_cast<uint64_t*>(&ctl->queue), 0, 1, st));
   if (nitems == 0) return FG_OK;
   const int ef = bi ? bi->ef_max : (int)P->ef_h;
-  const int hslots = beam_table_slots(ef, false, table_request(P), beam_chunks_per_lane(s));
+  const int hslots = beam_table_slots(ef, false, table_request(P, beam_chunks_per_lane(s)), beam_chunks_per_lane(s));
   const int screen = search_screen(P->screen);
   int grid = beam_grid(s, ef, false, hslots, screen, (int)P->waves_per_cu);
   if (grid <= 0) return set_error("no beam kernel for this row size / ef_h"), FG_EUNSUPPORTED;
