@@ -33,6 +33,10 @@ DATASETS = {
     "hub-f32-6000": lambda: (gen.hub_f32(6000, 32, 2), "l2"),
     # a hub with ~1500 finalize candidates: finalize's second on-chip tier
     "hub-f32-1500": lambda: (gen.hub_f32(1500, 32, 3), "l2"),
+    # the longest rows each kind takes, and a set for every parameter at its bound
+    "f32-d1024-400": lambda: (gen.powerlaw_f32(400, 1024, 8, 7), "l2"),
+    "u8-d256-1500": lambda: (gen.small_u8(1500, 256, 8, hi=256), "l2"),
+    "f32-d32-600": lambda: (gen.workload_data(gen.CFG1, 600), "l2"),
 }
 
 
@@ -148,6 +152,11 @@ BUILDS = [
     ("hub-u8-6000", 4, 32, 16, 1.2, 2),
     ("hub-f32-6000", 4, 32, 16, 1.2, 3),
     ("hub-f32-1500", 4, 32, 16, 1.2, 2),
+    ("f32-d1024-400", 4, 32, 16, 1.2, 2),
+    ("u8-d256-1500", 4, 32, 16, 1.2, 2),
+    # T, ef_h and R at their largest (64, 256, 1024): rows wider than every
+    # on-chip tier of the merge and finalize
+    ("f32-d32-600", 64, 256, 1024, 1.2, 4),
 ]
 
 
