@@ -118,6 +118,7 @@ struct WsMap {
   size_t xs, xs_err, xs_norm, xs_sinv;      // screened harvest (last: only they depend on d)
   size_t xsp;                               // the bfloat16 split (interleaved hi/lo)
   int64_t xsp_stride;
+  size_t sched;                             // every block's points in scaffold order
   size_t gram;                              // Gram-tile prune scratch (float32, d > 256)
   size_t norm;                              // |x_i|^2 per row for it
   int64_t xs_stride;
@@ -174,6 +175,7 @@ WsMap ws_map(int64_t n, const fg_params* p, int d = 0) {
   m.cnt = take(un * 4);
   m.tparent = take(T * un * 4);
   m.roots = take(64 * 4);
+  m.sched = take(un * 4);
   sat_workspace_bytes(n, (uint32_t)T, &m.satw);
   m.sat = take(m.satw.total);
   if (p && d > 256 && d % 4 == 0 && d <= 1024) {
@@ -202,6 +204,7 @@ struct Ctl {
   unsigned long long fin[3];         // finalize: candidate distances, prune pairs, exact rechecks
   uint32_t nbig, nmid;               // rows sent to the big-row paths / finalize's second tier
   int status;                        // 1 expanded-set overflow
+  unsigned int xq[8];                // the ordered harvest's per-XCD queues
 };
 
 hipError_t g_last_hip = hipSuccess;
@@ -238,7 +241,7 @@ struct BatchInfo {
 fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* ids,
                          const uint32_t* roots, const fg_params* P, uint32_t b, uint32_t* rows,
                          uint32_t* cnt, void* ws, const WsMap& m, hipStream_t st,
-                         const BatchInfo* bi = nullptr) {
+                         const BatchInfo* bi = nullptr, const uint32_t* order = nullptr) {
   const uint32_t Be = b_eff(P);
   int64_t nitems = s.n > (int64_t)b ? (s.n - (int64_t)b + Be - 1) / Be : 0;
   Ctl* ctl = reinterpret_cast<Ctl*>(at(ws, m.ctl));
@@ -266,7 +269,12 @@ fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* id
   a.rows = rows;
   a.cnt = cnt;
   a.nitems = nitems;
+  a.order = order;
   a.queue = &ctl->queue;
+  if (order) {
+    FG_HIP(fill_u32(ctl->xq, 0, 8, st));
+    a.xqueue = ctl->xq;
+  }
   a.Ebuf = reinterpret_cast<uint64_t*>(at(ws, m.ebuf));
   a.Ecap = hslots / 2;  // the expanded set is sorted in the visited table's space
   a.spill_bits = reinterpret_cast<uint32_t*>(at(ws, m.bits));
@@ -849,6 +857,14 @@ fg_status fg_build_graph(const fg_data* data, uint64_t seed, const fg_params* pa
   }
   FG_TRY(scaffold_csr_launch(n, T, tparent, off[0], ids[0], ws_dev, m, st));
   FG_HIP(hipMemcpyAsync(out->spine_parent_dev, tparent, n * 4, hipMemcpyDeviceToDevice, st));
+  // Processing order of every block: tree 0's final bag layout, where each
+  // subtree's points lie together, so that searches running at the same
+  // time share targets in cache (the graph does not depend on it, Prop. 1).
+  uint32_t* sched = reinterpret_cast<uint32_t*>(at(ws_dev, m.sched));
+  FG_HIP(fill_u32(sched, FG_NONE, n, st));
+  FG_HIP(block_schedule(reinterpret_cast<const uint32_t*>(at(ws_dev, m.sat) + m.satw.perm), n - 1, Be, hroots[0],
+                        sched, reinterpret_cast<uint32_t*>(at(ws_dev, m.deg)),
+                        reinterpret_cast<uint64_t*>(at(ws_dev, m.aoff)), at(ws_dev, m.scan), st));
   FG_TRY(mark());
   FG_TRY(screen_launch(s, params, ws_dev, m, st));
   FG_TRY(mark());
@@ -860,9 +876,12 @@ fg_status fg_build_graph(const fg_data* data, uint64_t seed, const fg_params* pa
   int cur = 0;
   std::vector<unsigned long long> blk_evals;
   Ctl* ctl = reinterpret_cast<Ctl*>(at(ws_dev, m.ctl));
+  int64_t sched_base = 0;
   for (uint32_t b = 0; b < Be; b++) {
     FG_TRY(mark());
-    FG_TRY(harvest_launch(s, off[cur], ids[cur], roots, params, b, rows, cnt, ws_dev, m, st));
+    FG_TRY(harvest_launch(s, off[cur], ids[cur], roots, params, b, rows, cnt, ws_dev, m, st, nullptr,
+                          sched + sched_base));
+    sched_base += n > (int64_t)b ? (n - (int64_t)b + Be - 1) / Be : 0;
     FG_TRY(mark());
     if (timings) {
       unsigned long long e = 0;

@@ -100,7 +100,14 @@ struct BeamArgs {
   uint32_t* out_evals;
   // work
   int64_t nitems;
+  // harvest: the block's points in processing order (NULL: p = b + item * B);
+  // the graph does not depend on the order (Prop. 1), locality does
+  const uint32_t* order;
   unsigned long long* queue;
+  // with order: eight counters, one slice of the order per XCD (workgroup i
+  // runs on XCD i mod 8), so each L2 sees neighbouring points; a wave whose
+  // slice is done takes from the next one (NULL: the single queue)
+  unsigned int* xqueue;
   // scratch (per wave slot)
   uint64_t* Ebuf;
   int Ecap;
@@ -771,13 +778,36 @@ k_beam(BeamArgs A) {
 #endif
   FG_T0();
 
+  // wave-uniform scalars (the slice walk stays in scalar registers)
+  int xq = (int)(blockIdx.x & 7), xfail = 0;
+  const int64_t xslice = (A.nitems + 7) / 8;
   for (;;) {
     unsigned long long item = 0;
-    if (lane == 0) item = atomicAdd(A.queue, 1ull);
-    item = __shfl(item, 0, 64);
-    if ((int64_t)item >= A.nitems) break;
+    if (A.xqueue) {
+      int64_t it = -1;
+      while (xfail < 8) {
+        unsigned int k = 0;
+        if (lane == 0) k = atomicAdd(&A.xqueue[xq], 1u);
+        k = (unsigned int)__builtin_amdgcn_readfirstlane((int)k);
+        const int64_t c = (int64_t)xq * xslice + (int64_t)k;
+        if ((int64_t)k < xslice && c < A.nitems) {
+          it = c;
+          break;
+        }
+        xq = (xq + 1) & 7;  // this slice is done: the next one (each is visited once)
+        xfail++;
+      }
+      if (it < 0) break;
+      item = (unsigned long long)it;
+    } else {
+      if (lane == 0) item = atomicAdd(A.queue, 1ull);
+      item = __shfl(item, 0, 64);
+      if ((int64_t)item >= A.nitems) break;
+    }
 
-    const int64_t p = SEARCH ? (int64_t)item : A.b + (int64_t)item * A.B;
+    const int64_t p = SEARCH ? (int64_t)item : (A.order ? (int64_t)A.order[item] : A.b + (int64_t)item * A.B);
+    if constexpr (!SEARCH)
+      if (p >= A.n) continue;  // an order slot left empty (never, for a permutation)
     int ef = A.ef;
     const uint32_t* roots = A.roots;
     if constexpr (!SEARCH) {

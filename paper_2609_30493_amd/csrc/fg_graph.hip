@@ -536,6 +536,45 @@ __global__ void __launch_bounds__(64) k_merge_big(const uint32_t* big, const KSe
 
 }  // namespace
 
+namespace {
+__global__ void k_block_flags(const uint32_t* order, int64_t len, uint32_t B, uint32_t b, uint32_t* flags) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x)
+    flags[i] = order[i] % B == b ? 1u : 0u;
+}
+__global__ void k_block_scatter(const uint32_t* order, int64_t len, uint32_t B, uint32_t b, const uint64_t* pos,
+                                uint32_t* out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t p = order[i];
+    if (p % B == b) out[pos[i]] = p;
+  }
+}
+}  // namespace
+
+hipError_t block_schedule(const uint32_t* order, int64_t len, uint32_t B, uint32_t last, uint32_t* sched,
+                          uint32_t* flags, uint64_t* pos, void* scratch, hipStream_t st) {
+  const int64_t n = len + 1;
+  int64_t base = 0;
+  for (uint32_t b = 0; b < B; b++) {
+    const int64_t nb = n > (int64_t)b ? (n - (int64_t)b + B - 1) / B : 0;
+    if (len > 0) {
+      k_block_flags<<<blocks_for(len, 1024), 256, 0, st>>>(order, len, B, b, flags);
+      hipError_t e = hipGetLastError();
+      if (e == hipSuccess) e = exclusive_scan_u32_u64(flags, pos, len, scratch, st);
+      if (e != hipSuccess) return e;
+      k_block_scatter<<<blocks_for(len, 1024), 256, 0, st>>>(order, len, B, b, pos, sched + base);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    if (last % B == b && nb > 0) {  // the one id the order leaves out closes its block
+      hipError_t e = fill_u32(sched + base + nb - 1, last, 1, st);
+      if (e != hipSuccess) return e;
+    }
+    base += nb;
+  }
+  return hipSuccess;
+}
+
 hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   k_fill_u32<<<blocks_for(count, 1024), 256, 0, st>>>(p, v, count);
