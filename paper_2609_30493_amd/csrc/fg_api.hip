@@ -411,7 +411,7 @@ fg_status scaffold_csr_launch(int64_t n, uint32_t T, const uint32_t* tparent, ui
 
 fg_status finalize_launch(const Shape& s, const uint32_t* rows, const uint32_t* cnt, const fg_params* P,
                           uint32_t* g_nbrs, uint32_t* g_cnt, void* ws, const WsMap& m, hipStream_t st,
-                          const BatchInfo* bi = nullptr) {
+                          const BatchInfo* bi = nullptr, const uint32_t* order = nullptr) {
   const int64_t n = s.n;
   const int R = (int)P->R;
   uint32_t* deg = reinterpret_cast<uint32_t*>(at(ws, m.deg));
@@ -445,6 +445,7 @@ fg_status finalize_launch(const Shape& s, const uint32_t* rows, const uint32_t* 
     f.inst_of = bi->inst_of;
     f.inst_q = bi->inst_q;
   }
+  f.order = order;
   if (f.gram && m.xsp) f.split = GramSplit{reinterpret_cast<const uint8_t*>(at(ws, m.xsp)), m.xsp_stride};
   f.status = &ctl->status;
   f.big = reinterpret_cast<uint32_t*>(at(ws, m.big));
@@ -897,8 +898,11 @@ fg_status fg_build_graph(const fg_data* data, uint64_t seed, const fg_params* pa
     FG_TRY(mark());
   }
 
-  // Finalize.
-  FG_TRY(finalize_launch(s, rows, cnt, params, out->nbrs_dev, out->cnt_dev, ws_dev, m, st));
+  // Finalize, in tree 0's layout order (neighbouring points together).
+  if (n > 1)
+    FG_HIP(hipMemcpyAsync(sched, at(ws_dev, m.sat) + m.satw.perm, (n - 1) * 4, hipMemcpyDeviceToDevice, st));
+  FG_HIP(fill_u32(sched + n - 1, hroots[0], 1, st));
+  FG_TRY(finalize_launch(s, rows, cnt, params, out->nbrs_dev, out->cnt_dev, ws_dev, m, st, nullptr, sched));
   FG_TRY(mark());
   Ctl c;
   FG_TRY(read_ctl(ws_dev, m, st, &c));

@@ -137,6 +137,8 @@ struct FinalizeArgs {
   // own rows (NULL: every row has X.Q chunks)
   const uint16_t* inst_of;
   const int* inst_q;
+  // the points in processing order (a permutation of [0, n); NULL: id order)
+  const uint32_t* order;
 };
 struct FinalizeBig {
   KSeg* segs;
