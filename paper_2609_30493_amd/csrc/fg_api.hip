@@ -119,6 +119,7 @@ struct WsMap {
   size_t xsp;                               // the bfloat16 split (interleaved hi/lo)
   int64_t xsp_stride;
   size_t sched;                             // every block's points in scaffold order
+  size_t rank;                              // each id's position in that order
   size_t gram;                              // Gram-tile prune scratch (float32, d > 256)
   size_t norm;                              // |x_i|^2 per row for it
   int64_t xs_stride;
@@ -176,6 +177,7 @@ WsMap ws_map(int64_t n, const fg_params* p, int d = 0) {
   m.tparent = take(T * un * 4);
   m.roots = take(64 * 4);
   m.sched = take(un * 4);
+  m.rank = take(un * 4);
   sat_workspace_bytes(n, (uint32_t)T, &m.satw);
   m.sat = take(m.satw.total);
   if (p && d > 256 && d % 4 == 0 && d <= 1024) {
@@ -241,7 +243,8 @@ struct BatchInfo {
 fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* ids,
                          const uint32_t* roots, const fg_params* P, uint32_t b, uint32_t* rows,
                          uint32_t* cnt, void* ws, const WsMap& m, hipStream_t st,
-                         const BatchInfo* bi = nullptr, const uint32_t* order = nullptr) {
+                         const BatchInfo* bi = nullptr, const uint32_t* order = nullptr,
+                         const uint32_t* rank = nullptr) {
   const uint32_t Be = b_eff(P);
   int64_t nitems = s.n > (int64_t)b ? (s.n - (int64_t)b + Be - 1) / Be : 0;
   Ctl* ctl = reinterpret_cast<Ctl*>(at(ws, m.ctl));
@@ -270,6 +273,7 @@ fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* id
   a.cnt = cnt;
   a.nitems = nitems;
   a.order = order;
+  a.rank = rank;
   a.queue = &ctl->queue;
   if (order) {
     FG_HIP(fill_u32(ctl->xq, 0, 8, st));
@@ -866,6 +870,8 @@ fg_status fg_build_graph(const fg_data* data, uint64_t seed, const fg_params* pa
   FG_HIP(block_schedule(reinterpret_cast<const uint32_t*>(at(ws_dev, m.sat) + m.satw.perm), n - 1, Be, hroots[0],
                         sched, reinterpret_cast<uint32_t*>(at(ws_dev, m.deg)),
                         reinterpret_cast<uint64_t*>(at(ws_dev, m.aoff)), at(ws_dev, m.scan), st));
+  uint32_t* rank = reinterpret_cast<uint32_t*>(at(ws_dev, m.rank));
+  FG_HIP(rank_of(reinterpret_cast<const uint32_t*>(at(ws_dev, m.sat) + m.satw.perm), n - 1, hroots[0], rank, st));
   FG_TRY(mark());
   FG_TRY(screen_launch(s, params, ws_dev, m, st));
   FG_TRY(mark());
@@ -881,7 +887,7 @@ fg_status fg_build_graph(const fg_data* data, uint64_t seed, const fg_params* pa
   for (uint32_t b = 0; b < Be; b++) {
     FG_TRY(mark());
     FG_TRY(harvest_launch(s, off[cur], ids[cur], roots, params, b, rows, cnt, ws_dev, m, st, nullptr,
-                          sched + sched_base));
+                          sched + sched_base, rank));
     sched_base += n > (int64_t)b ? (n - (int64_t)b + Be - 1) / Be : 0;
     FG_TRY(mark());
     if (timings) {

@@ -103,6 +103,11 @@ struct BeamArgs {
   // harvest: the block's points in processing order (NULL: p = b + item * B);
   // the graph does not depend on the order (Prop. 1), locality does
   const uint32_t* order;
+  // visited bitsets indexed by position in the processing order instead of
+  // by id (NULL: by id): a search's visits then cluster in few lines.  Used
+  // by rows of 2..4 chunks per lane, where it measured faster; the extra
+  // dependent load costs more than it saves for one-chunk and 16-chunk rows.
+  const uint32_t* rank;
   unsigned long long* queue;
   // with order: eight counters, one slice of the order per XCD (workgroup i
   // runs on XCD i mod 8), so each L2 sees neighbouring points; a wave whose
@@ -770,6 +775,7 @@ k_beam(BeamArgs A) {
   constexpr int HCAP = HSLOTS / 2 - 64;  // load <= 1/2; checked after every 64 insertions
   // rows in flight per lane group, sized to the register budget above
   constexpr int kRB = (NCH >= 16) ? 1 : (NCH == 1 ? (HSLOTS == 1024 ? 8 : 12) : 16 / NCH);
+  constexpr bool kRankBits = !SEARCH && NCH >= 2 && NCH <= 4;  // see BeamArgs::rank
   RowSet X{A.x, A.stride, A.Q};
 
   unsigned long long my_evals = 0, my_exp = 0, my_pe = 0, my_spilled = 0, my_rej = 0, my_rc = 0;
@@ -877,6 +883,8 @@ k_beam(BeamArgs A) {
             for (int i = lane; i < HSLOTS; i += 64) {
               uint32_t v = S.htab[i];
               if (v != FG_NONE) {
+                if constexpr (kRankBits)
+                  if (A.rank) v = A.rank[v];
                 atomicOr(&bits[v >> 5], 1u << (v & 31));
                 uint32_t idx = atomicAdd(&S.nspill, 1u);
                 if ((int)idx < A.spill_cap) slist[idx] = v;
@@ -888,16 +896,32 @@ k_beam(BeamArgs A) {
         }
         FG_TICK(0);
         uint32_t old[4];
+        if constexpr (kRankBits) {
+          uint32_t bi[4];
 #pragma unroll
-        for (int k = 0; k < 4; k++)
-          if (need[k]) old[k] = atomicOr(&bits[u[k] >> 5], 1u << (u[k] & 31));
-#pragma unroll
-        for (int k = 0; k < 4; k++)
-          if (need[k] && !(old[k] & (1u << (u[k] & 31)))) {
-            isnew[k] = true;
-            uint32_t idx = atomicAdd(&S.nspill, 1u);
-            if ((int)idx < A.spill_cap) slist[idx] = u[k];
+          for (int k = 0; k < 4; k++) {
+            bi[k] = need[k] && A.rank ? A.rank[u[k]] : u[k];  // the bit of u
+            if (need[k]) old[k] = atomicOr(&bits[bi[k] >> 5], 1u << (bi[k] & 31));
           }
+#pragma unroll
+          for (int k = 0; k < 4; k++)
+            if (need[k] && !(old[k] & (1u << (bi[k] & 31)))) {
+              isnew[k] = true;
+              uint32_t idx = atomicAdd(&S.nspill, 1u);
+              if ((int)idx < A.spill_cap) slist[idx] = bi[k];
+            }
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; k++)
+            if (need[k]) old[k] = atomicOr(&bits[u[k] >> 5], 1u << (u[k] & 31));
+#pragma unroll
+          for (int k = 0; k < 4; k++)
+            if (need[k] && !(old[k] & (1u << (u[k] & 31)))) {
+              isnew[k] = true;
+              uint32_t idx = atomicAdd(&S.nspill, 1u);
+              if ((int)idx < A.spill_cap) slist[idx] = u[k];
+            }
+        }
         FG_TICK(1);
         int nnew = 0;
 #pragma unroll
@@ -1036,7 +1060,7 @@ k_beam(BeamArgs A) {
       // Clear with atomics: the next query sets bits with atomics at L2, and
       // plain stores are not ordered against them.
       if ((int)ns <= A.spill_cap) {
-        for (uint32_t t = lane; t < ns; t += 64) atomicAnd(&bits[slist[t] >> 5], 0u);
+        for (uint32_t t = lane; t < ns; t += 64) atomicAnd(&bits[slist[t] >> 5], 0u);  // listed bits' words
       } else {
         for (int64_t t = lane; t < A.spill_words; t += 64) atomicAnd(&bits[t], 0u);
       }

@@ -549,7 +549,16 @@ __global__ void k_block_scatter(const uint32_t* order, int64_t len, uint32_t B, 
     if (p % B == b) out[pos[i]] = p;
   }
 }
+__global__ void k_rank_of(const uint32_t* order, int64_t len, uint32_t last, uint32_t* rank) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= len; i += (int64_t)gridDim.x * blockDim.x)
+    rank[i < len ? order[i] : last] = (uint32_t)i;
+}
 }  // namespace
+
+hipError_t rank_of(const uint32_t* order, int64_t len, uint32_t last, uint32_t* rank, hipStream_t st) {
+  k_rank_of<<<blocks_for(len + 1, 1024), 256, 0, st>>>(order, len, last, rank);
+  return hipGetLastError();
+}
 
 hipError_t block_schedule(const uint32_t* order, int64_t len, uint32_t B, uint32_t last, uint32_t* sched,
                           uint32_t* flags, uint64_t* pos, void* scratch, hipStream_t st) {

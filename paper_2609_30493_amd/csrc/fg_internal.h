@@ -68,6 +68,8 @@ hipError_t fill_u64(uint64_t* p, uint64_t v, int64_t count, hipStream_t st);
 // (len + 1) are scratch.
 hipError_t block_schedule(const uint32_t* order, int64_t len, uint32_t B, uint32_t last, uint32_t* sched,
                           uint32_t* flags, uint64_t* pos, void* scratch, hipStream_t st);
+// rank[order[i]] = i for i < len, rank[last] = len (order: every id but last).
+hipError_t rank_of(const uint32_t* order, int64_t len, uint32_t last, uint32_t* rank, hipStream_t st);
 // Exclusive scan of `count` uint32 values into uint64 offsets (count+1 entries).
 size_t scan_scratch_bytes(int64_t count);
 hipError_t exclusive_scan_u32_u64(const uint32_t* in, uint64_t* out, int64_t count,
