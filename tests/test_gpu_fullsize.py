@@ -1,8 +1,9 @@
 """The hot path at the full size and launch configuration that bench.py
 times (the SIFT-shaped uint8 build: n = 10^6, d = 128, T = 8, B = 8,
 ef_h = 64, R = 32, alpha = 1.2, a 1024-slot visited table, as many
-searches as fit), and the GIST-shaped float32 build (d = 960, the
-matrix-core prune and scaffold tiles) at n = 200,000, checked where the
+searches as fit), the GIST-shaped float32 build (d = 960, the matrix-core
+prune and scaffold tiles) and the GloVe-shaped cosine build (d = 100, the
+order-indexed visited bitsets) at n = 200,000, checked where the
 oracle cannot rebuild the whole graph in seconds: on sampled rows the oracle
 computes one by one (exact declared-order distances, its own prune, its
 roots) and through properties that hold at any size."""
@@ -17,7 +18,8 @@ pytestmark = pytest.mark.gpu
 
 SAMPLE = 300
 # workload, n, visited-table slots (0: the library's default)
-CASES = {"sift-1M": (gen.CFG2, 1_000_000, 1024), "gist-200k": (gen.CFG4, 200_000, 0)}
+CASES = {"sift-1M": (gen.CFG2, 1_000_000, 1024), "gist-200k": (gen.CFG4, 200_000, 0),
+         "glove-200k": (gen.CFG3, 200_000, 0)}
 
 
 @pytest.fixture(scope="module", params=list(CASES))
