@@ -867,7 +867,7 @@ fg_status fg_build_graph(const fg_data* data, uint64_t seed, const fg_params* pa
   // time share targets in cache (the graph does not depend on it, Prop. 1).
   uint32_t* sched = reinterpret_cast<uint32_t*>(at(ws_dev, m.sched));
   FG_HIP(fill_u32(sched, FG_NONE, n, st));
-  FG_HIP(block_schedule(reinterpret_cast<const uint32_t*>(at(ws_dev, m.sat) + m.satw.perm), n - 1, Be, hroots[0],
+  FG_HIP(block_schedule(reinterpret_cast<const uint32_t*>(at(ws_dev, m.sat) + m.satw.perm), n - 1, n, Be, hroots[0],
                         sched, reinterpret_cast<uint32_t*>(at(ws_dev, m.deg)),
                         reinterpret_cast<uint64_t*>(at(ws_dev, m.aoff)), at(ws_dev, m.scan), st));
   uint32_t* rank = reinterpret_cast<uint32_t*>(at(ws_dev, m.rank));
@@ -1233,6 +1233,28 @@ fg_status fg_build_graph_batched(const fg_data* const* data, const fg_params* co
   r = scaffold_csr_launch(N, T, tparent, off[0], ids[0], ws_dev, m, st);
   if (r) return r;
 
+  // Processing order: each instance's tree-0 layout and root, instance after
+  // instance (the padding ids between instances are in no block's list), and
+  // each id's position in it for the order-indexed visited bitsets.
+  uint32_t* sched = reinterpret_cast<uint32_t*>(at(ws_dev, m.sched));
+  uint32_t* rank = reinterpret_cast<uint32_t*>(at(ws_dev, m.rank));
+  {
+    uint32_t* ord = reinterpret_cast<uint32_t*>(at(ws_dev, m.deg));
+    const uint32_t* perm0 = reinterpret_cast<const uint32_t*>(at(ws_dev, m.sat) + m.satw.perm);
+    int64_t len = 0;
+    for (uint32_t i = 0; i < count; i++) {
+      const int64_t ni = data[i]->n;
+      if (ni > 1)
+        FG_HIP(hipMemcpyAsync(ord + len, perm0 + bp.off[i], (ni - 1) * 4, hipMemcpyDeviceToDevice, st));
+      FG_HIP(fill_u32(ord + len + ni - 1, (uint32_t)bp.off[i] + hroots_local[(size_t)i * T], 1, st));
+      len += ni;
+    }
+    FG_HIP(fill_u32(sched, FG_NONE, N, st));
+    FG_HIP(block_schedule(ord, len, N, Be, FG_NONE, sched, reinterpret_cast<uint32_t*>(at(ws_dev, m.cursor)),
+                          reinterpret_cast<uint64_t*>(at(ws_dev, m.aoff)), at(ws_dev, m.scan), st));
+    FG_HIP(rank_of(ord, len, FG_NONE, rank, st));
+  }
+
   // Blocks.
   const BatchInfo bi{inst_of, inst_roots, inst_ef, bp.ef_max, inst_q};
   auto init_rows = [&](hipStream_t s_) -> fg_status {
@@ -1243,9 +1265,12 @@ fg_status fg_build_graph_batched(const fg_data* const* data, const fg_params* co
   };
   auto blocks = [&](hipStream_t s_, bool device_only) -> fg_status {
     int cur = 0;
+    int64_t base = 0;
     for (uint32_t b = 0; b < Be; b++) {
-      fg_status rr = harvest_launch(bp.s, off[cur], ids[cur], inst_roots, &bp.P, b, rows, cnt, ws_dev, m, s_, &bi);
+      fg_status rr = harvest_launch(bp.s, off[cur], ids[cur], inst_roots, &bp.P, b, rows, cnt, ws_dev, m, s_, &bi,
+                                    sched + base, rank);
       if (rr) return rr;
+      base += N > (int64_t)b ? (N - (int64_t)b + Be - 1) / Be : 0;
       if (b + 1 < Be) {
         rr = merge_launch(N, off[cur], ids[cur], rows, cnt, (int)R, b, Be, off[cur ^ 1], ids[cur ^ 1], ws_dev, m,
                           s_, device_only);

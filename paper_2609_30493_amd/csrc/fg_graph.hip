@@ -551,7 +551,7 @@ __global__ void k_block_scatter(const uint32_t* order, int64_t len, uint32_t B, 
 }
 __global__ void k_rank_of(const uint32_t* order, int64_t len, uint32_t last, uint32_t* rank) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= len; i += (int64_t)gridDim.x * blockDim.x)
-    rank[i < len ? order[i] : last] = (uint32_t)i;
+    if (i < len || last != FG_NONE) rank[i < len ? order[i] : last] = (uint32_t)i;
 }
 }  // namespace
 
@@ -560,9 +560,8 @@ hipError_t rank_of(const uint32_t* order, int64_t len, uint32_t last, uint32_t* 
   return hipGetLastError();
 }
 
-hipError_t block_schedule(const uint32_t* order, int64_t len, uint32_t B, uint32_t last, uint32_t* sched,
-                          uint32_t* flags, uint64_t* pos, void* scratch, hipStream_t st) {
-  const int64_t n = len + 1;
+hipError_t block_schedule(const uint32_t* order, int64_t len, int64_t n, uint32_t B, uint32_t last,
+                          uint32_t* sched, uint32_t* flags, uint64_t* pos, void* scratch, hipStream_t st) {
   int64_t base = 0;
   for (uint32_t b = 0; b < B; b++) {
     const int64_t nb = n > (int64_t)b ? (n - (int64_t)b + B - 1) / B : 0;
@@ -575,7 +574,7 @@ hipError_t block_schedule(const uint32_t* order, int64_t len, uint32_t B, uint32
       e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
-    if (last % B == b && nb > 0) {  // the one id the order leaves out closes its block
+    if (last != FG_NONE && last % B == b && nb > 0) {  // the one id the order leaves out closes its block
       hipError_t e = fill_u32(sched + base + nb - 1, last, 1, st);
       if (e != hipSuccess) return e;
     }

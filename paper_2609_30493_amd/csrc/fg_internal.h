@@ -62,13 +62,15 @@ hipError_t localize_graph(const uint32_t* nbrs, const uint32_t* cnt, const uint3
                           int64_t o, uint32_t* out_nbrs, uint32_t* out_cnt, uint32_t* out_parent, hipStream_t st);
 hipError_t fill_u64(uint64_t* p, uint64_t v, int64_t count, hipStream_t st);
 // The points of every block b (p mod B == b) in the order they appear in
-// `order` (a permutation of every id but `last`, len = n - 1 entries), block
-// after block into sched (n entries; block b starts at the sum of the
-// earlier blocks' sizes); `last` closes its block.  flags (len) and pos
-// (len + 1) are scratch.
-hipError_t block_schedule(const uint32_t* order, int64_t len, uint32_t B, uint32_t last, uint32_t* sched,
-                          uint32_t* flags, uint64_t* pos, void* scratch, hipStream_t st);
-// rank[order[i]] = i for i < len, rank[last] = len (order: every id but last).
+// `order` (len ids: every id of [0, n) but `last`, or with last =
+// 0xFFFFFFFF any set of distinct ids), block after block into sched (n
+// entries; block b starts at the sum of the earlier blocks' sizes in
+// [0, n)); `last` closes its block; slots no id fills keep their contents.
+// flags (len) and pos (len + 1) are scratch.
+hipError_t block_schedule(const uint32_t* order, int64_t len, int64_t n, uint32_t B, uint32_t last,
+                          uint32_t* sched, uint32_t* flags, uint64_t* pos, void* scratch, hipStream_t st);
+// rank[order[i]] = i for i < len, rank[last] = len (order: every id but last;
+// last = 0xFFFFFFFF: no last).
 hipError_t rank_of(const uint32_t* order, int64_t len, uint32_t last, uint32_t* rank, hipStream_t st);
 // Exclusive scan of `count` uint32 values into uint64 offsets (count+1 entries).
 size_t scan_scratch_bytes(int64_t count);
