@@ -152,6 +152,73 @@ def dsweep(args):
     print(json.dumps({"mode": "dsweep", "n": n, "rows": out, "loglog_exponents": fit}), flush=True)
 
 
+def wsweep(args):
+    """Throughput against working set (Sec. 5.2's prefix table): whole builds of
+    prefixes of one GloVe-shaped matrix (d = 100, unit rows, cosine, T=8 B=8
+    ef_h=128 R=64), from a few MB (inside the L2s and the Infinity Cache) to
+    past the 256 MB Infinity Cache, each beside the blocked kernel on the same
+    prefix (every point's 64 nearest inside leaves of 2048 consecutive rows on
+    matrix cores, squared L2 on the unit rows: the same Gram work).  The
+    prefixes are slices of one draw, so every smaller set is a true prefix of
+    the larger ones."""
+    w = gen.CFG3
+    sizes = [int(v) for v in args.sizes.split(",")] if args.sizes else \
+        [20_000, 50_000, 100_000, 200_000, 500_000, w.n]
+    N = max(sizes)
+    log(f"[wsweep] generating {N} x {w.d} rows ({w.recipe})")
+    x = gen.workload_data(w, N)
+    xd_all = torch.from_numpy(x).cuda()
+    row_bytes = xd_all.stride(0) * xd_all.element_size()
+    out = []
+    for n in sorted(sizes):
+        xd = xd_all[:n]
+        data = F.make_data(xd, "cosine")
+        params = F.make_params(w.T, w.ef_h, w.R, w.alpha, w.B)
+        ws = F.alloc_workspace(data, params)
+        u32 = lambda *sh: torch.full(sh, -1, dtype=torch.int32, device="cuda")  # noqa: E731
+        G = F.make_graph(u32(n, w.R), u32(n), u32(n), u32(w.T), w.T)
+        F.build_graph(data, w.build_seed, params, G, ws, timings=True)
+        runs = [F.build_graph(data, w.build_seed, params, G, ws, timings=True) for _ in range(args.reps)]
+        c = runs[0][0]
+        hms = float(np.median([t["harvest_ms"] for _, t in runs]))
+        bms = float(np.median([sum(t[k] for k in ("scaffold_ms", "harvest_ms", "merge_ms", "finalize_ms"))
+                               for _, t in runs]))
+        rate = c["harvest_evals"] / (hms / 1e3)
+        rec = {"n": n, "MB": n * row_bytes / 1e6, "harvest_evals": c["harvest_evals"], "harvest_ms": hms,
+               "build_ms": bms, "harvest_G_evals_per_s": rate / 1e9,
+               "evals_per_point": c["harvest_evals"] / n,
+               # one exact evaluation reads one row; at HBM peak that is 8e12 / row_bytes rows/s
+               "frac_of_hbm_row_rate": rate * row_bytes / 8e12}
+        del ws, G
+        S, R = 2048, 64
+        pairs = sum(min(S, n - l0) ** 2 for l0 in range(0, n, S))
+        dl2 = F.make_data(xd, "l2")
+        oi = torch.empty(n, R, dtype=torch.int32, device="cuda")
+        od = torch.empty(n, R, dtype=torch.float32, device="cuda")
+        for bf16 in (False, True):
+            lws = F.leaf_knn(dl2, S, R, bf16, oi, od)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(3):
+                F.leaf_knn(dl2, S, R, bf16, oi, od, lws)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 3
+            key = "bf16" if bf16 else "fp32"
+            rec[f"blocked_{key}_G_pairs_per_s"] = pairs / (ms / 1e3) / 1e9
+            rec[f"blocked_{key}_over_harvest"] = rec[f"blocked_{key}_G_pairs_per_s"] / rec["harvest_G_evals_per_s"]
+            del lws
+        log(f"[wsweep] {json.dumps(rec)}")
+        out.append(rec)
+        del oi, od, data, dl2
+        torch.cuda.empty_cache()
+    base = out[0]["harvest_G_evals_per_s"]
+    print(json.dumps({"mode": "wsweep", "workload": w.name, "row_bytes": row_bytes, "rows": out,
+                      "harvest_rate_largest_over_smallest": out[-1]["harvest_G_evals_per_s"] / base}),
+          flush=True)
+
+
 def ground_truth_f32(xd: torch.Tensor, qd: torch.Tensor, k: int, metric: str):
     """Exact k-NN distances in float64 (brute force on the device)."""
     x64 = xd.double()
@@ -358,14 +425,16 @@ def batched_compare(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", default="build", choices=("build", "dsweep", "screen", "batched"),
+    ap.add_argument("--mode", default="build", choices=("build", "dsweep", "screen", "batched", "wsweep"),
                     help="build: the benchmark line (default); dsweep: wall vs dimension; "
                          "screen: bf16 / fp8 screened builds against float32; "
-                         "batched: 64 instances built together against sequential builds")
+                         "batched: 64 instances built together against sequential builds; "
+                         "wsweep: throughput against working set (GloVe-shaped prefixes)")
     ap.add_argument("--instances", type=int, default=64, help="batched mode: instance count")
     ap.add_argument("--scale", type=float, default=1.0, help="batched mode: shrink every instance's n")
     ap.add_argument("--workloads", default="cfg3,cfg4", help="screen mode: cfg3, cfg4 or both")
-    ap.add_argument("--reps", type=int, default=3, help="screen mode: paired repetitions")
+    ap.add_argument("--reps", type=int, default=3, help="screen mode: paired repetitions; wsweep: timed builds per prefix")
+    ap.add_argument("--sizes", default="", help="wsweep mode: comma-separated prefix sizes")
     ap.add_argument("--forms", default="", help="screen mode: fg_screen values to compare with float32 "
                                                  "(default: all that apply)")
     ap.add_argument("--gpus", type=int, default=1)
@@ -392,6 +461,8 @@ def main():
         return screen_compare(args)
     if args.mode == "batched":
         return batched_compare(args)
+    if args.mode == "wsweep":
+        return wsweep(args)
 
     w = gen.CFG2
     n = args.n or w.n
