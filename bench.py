@@ -254,6 +254,108 @@ def recall_ladder_f32(data, G, ws, qd, true_d, k=10, target=0.95):
     return res
 
 
+LADDER = (10, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512)
+
+
+def d_at_recall(ladder, r):
+    """Distances per query at recall r (Sec. 2's quality measure): linear in
+    recall between the two adjacent beam widths whose recalls bracket r.
+    None when the sweep does not bracket r (its first width already reaches
+    r, or no width does)."""
+    for i, pt in enumerate(ladder):
+        if pt["recall"] >= r:
+            if i == 0:
+                return None
+            lo = ladder[i - 1]
+            if pt["recall"] == lo["recall"]:
+                return float(pt["evals_per_query"])
+            f = (r - lo["recall"]) / (pt["recall"] - lo["recall"])
+            return float(lo["evals_per_query"] + f * (pt["evals_per_query"] - lo["evals_per_query"]))
+    return None
+
+
+def completeness(x: torch.Tensor, nbrs: np.ndarray, cnt: np.ndarray, metric: str, sample: np.ndarray, k=10):
+    """Local completeness (Sec. 2): the fraction of a point's true k nearest
+    other points (float64 brute force on the device) present in its row."""
+    x64 = x.double()
+    xn = (x64 * x64).sum(1)
+    hit = 0
+    for s in range(0, len(sample), 128):
+        ids = torch.from_numpy(sample[s:s + 128].astype(np.int64)).cuda()
+        q = x64[ids]
+        ip = q @ x64.T
+        d = 1.0 - ip if metric == "cosine" else xn[ids][:, None] + xn[None, :] - 2.0 * ip
+        d[torch.arange(len(ids), device="cuda"), ids] = float("inf")
+        tk = torch.topk(d, k, dim=1, largest=False).indices.cpu().numpy()
+        for j, p in enumerate(sample[s:s + 128]):
+            row = set(nbrs[p, :cnt[p]].tolist())
+            hit += sum(int(t) in row for t in tk[j])
+    return hit / (k * len(sample))
+
+
+def quality(args):
+    """The quality columns of Tab. 2 for arms of T (trees) and B (blocks) on
+    the GloVe-shaped workload: build time and evaluations, local
+    completeness, the recall@10 ladder with distances and queries per second
+    at each beam width, and d@0.95 / d@0.97 against the first arm."""
+    w = gen.CFG3
+    n = args.n or w.n
+    metric = "cosine" if w.metric == "cosine" else "l2"
+    arms = [tuple(int(v) for v in a.split(":")) for a in args.arms.split(",")]
+    log(f"[quality] generating {n} x {w.d} rows and {w.nq} queries")
+    xd = torch.from_numpy(gen.workload_data(w, n)).cuda()
+    qd = torch.from_numpy(gen.workload_queries(w)).cuda()
+    true_d = ground_truth_f32(xd, qd, 10, metric).cpu().numpy()
+    kth = true_d[:, -1:]
+    tol = 1e-5 * np.abs(kth) + 1e-6
+    sample = np.random.default_rng(17).choice(n, min(n, 2000), replace=False)
+    data = F.make_data(xd, metric)
+    nq = qd.shape[0]
+    out = []
+    for T, B, ef in arms:
+        params = F.make_params(T, ef, w.R, w.alpha, B)
+        ws = F.alloc_workspace(data, params)
+        u32 = lambda *sh: torch.full(sh, -1, dtype=torch.int32, device="cuda")  # noqa: E731
+        G = F.make_graph(u32(n, w.R), u32(n), u32(n), u32(T), T)
+        F.build_graph(data, w.build_seed, params, G, ws, timings=True)
+        c, t = F.build_graph(data, w.build_seed, params, G, ws, timings=True)
+        rec = {"arm": f"T{T}/ef_h {ef} B={B}", "T": T, "B": B, "ef_h": ef,
+               "build_s": sum(t[k] for k in ("scaffold_ms", "harvest_ms", "merge_ms", "finalize_ms")) / 1e3,
+               "G_dist": (c["scaffold_evals"] + c["harvest_evals"] + c["finalize_evals"]) / 1e9,
+               "hash": hex(F.graph_hash(G))}
+        nb, cn = G._keep[0].cpu().numpy().view(np.uint32), G._keep[1].cpu().numpy().view(np.uint32)
+        rec["completeness"] = completeness(xd, nb, cn, metric, sample)
+        ladder = []
+        oi = torch.empty(nq, 10, dtype=torch.int32, device="cuda")
+        od = torch.empty(nq, 10, dtype=torch.float32, device="cuda")
+        oe = torch.empty(nq, dtype=torch.int32, device="cuda")
+        for L in LADDER:
+            F.search(data, G, qd, 10, L, oi, od, oe, ws)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            F.search(data, G, qd, 10, L, oi, od, oe, ws)
+            e1.record()
+            torch.cuda.synchronize()
+            found = od.cpu().numpy().astype(np.float64)
+            ladder.append({"L": L, "recall": float(np.mean(found <= kth + tol)),
+                           "evals_per_query": float(oe.cpu().numpy().mean()),
+                           "qps": nq / (e0.elapsed_time(e1) / 1e3)})
+        rec["ladder"] = ladder
+        for r in (0.95, 0.97):
+            rec[f"d@{r}"] = d_at_recall(ladder, r)
+        log(f"[quality] {json.dumps({k: v for k, v in rec.items() if k != 'ladder'})}")
+        out.append(rec)
+        del ws, G
+        torch.cuda.empty_cache()
+    for r in (0.95, 0.97):
+        base = out[0][f"d@{r}"]
+        for rec in out:
+            v = rec[f"d@{r}"]
+            rec[f"d@{r}_rel"] = None if v is None or base is None else v / base
+    print(json.dumps({"mode": "quality", "workload": w.name, "n": n, "queries": nq, "arms": out}), flush=True)
+
+
 def hodges_lehmann(logr: np.ndarray) -> float:
     w = [(logr[i] + logr[j]) / 2 for i in range(len(logr)) for j in range(i, len(logr))]
     return float(np.exp(np.median(w)))
@@ -425,16 +527,19 @@ def batched_compare(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", default="build", choices=("build", "dsweep", "screen", "batched", "wsweep"),
+    ap.add_argument("--mode", default="build", choices=("build", "dsweep", "screen", "batched", "wsweep", "quality"),
                     help="build: the benchmark line (default); dsweep: wall vs dimension; "
                          "screen: bf16 / fp8 screened builds against float32; "
                          "batched: 64 instances built together against sequential builds; "
-                         "wsweep: throughput against working set (GloVe-shaped prefixes)")
+                         "wsweep: throughput against working set (GloVe-shaped prefixes); "
+                         "quality: completeness, recall ladder and d@r for T/B arms")
     ap.add_argument("--instances", type=int, default=64, help="batched mode: instance count")
     ap.add_argument("--scale", type=float, default=1.0, help="batched mode: shrink every instance's n")
     ap.add_argument("--workloads", default="cfg3,cfg4", help="screen mode: cfg3, cfg4 or both")
     ap.add_argument("--reps", type=int, default=3, help="screen mode: paired repetitions; wsweep: timed builds per prefix")
     ap.add_argument("--sizes", default="", help="wsweep mode: comma-separated prefix sizes")
+    ap.add_argument("--arms", default="8:8:128,8:1:128,8:32:128,16:8:128",
+                    help="quality mode: comma-separated T:B:ef_h arms (the first is the reference)")
     ap.add_argument("--forms", default="", help="screen mode: fg_screen values to compare with float32 "
                                                  "(default: all that apply)")
     ap.add_argument("--gpus", type=int, default=1)
@@ -463,6 +568,8 @@ def main():
         return batched_compare(args)
     if args.mode == "wsweep":
         return wsweep(args)
+    if args.mode == "quality":
+        return quality(args)
 
     w = gen.CFG2
     n = args.n or w.n
