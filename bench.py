@@ -548,7 +548,7 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override n (default: the workload's)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=100_000)
+    ap.add_argument("--cpu-sample", type=int, default=300_000)
     ap.add_argument("--table", type=int, default=1024, choices=(0, 1024, 2048, 4096),
                     help="on-chip visited-table slots per search (0 = library default); 1024 lets "
                          "four searches share each SIMD on this workload")
