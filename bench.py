@@ -160,10 +160,16 @@ def wsweep(args):
     prefix (every point's 64 nearest inside leaves of 2048 consecutive rows on
     matrix cores, squared L2 on the unit rows: the same Gram work).  The
     prefixes are slices of one draw, so every smaller set is a true prefix of
-    the larger ones."""
-    w = gen.CFG3
-    sizes = [int(v) for v in args.sizes.split(",")] if args.sizes else \
+    the larger ones.  With --sweep-workload u8 the same over the 128-byte
+    uint8 rows of the benchmark line's workload (T=8 B=8 ef_h=64 R=32, its
+    1024-slot visited table), 250,000 to 4,000,000 rows (32 to 512 MB), the
+    blocked kernel on a float32 copy of the rows."""
+    w = gen.CFG2 if args.sweep_workload == "u8" else gen.CFG3
+    default = [250_000, 500_000, 1_000_000, 2_000_000, 4_000_000] if w is gen.CFG2 else \
         [20_000, 50_000, 100_000, 200_000, 500_000, w.n]
+    sizes = [int(v) for v in args.sizes.split(",")] if args.sizes else default
+    metric = "cosine" if w.metric == "cosine" else "l2"
+    table = 1024 if w is gen.CFG2 else 0
     N = max(sizes)
     log(f"[wsweep] generating {N} x {w.d} rows ({w.recipe})")
     x = gen.workload_data(w, N)
@@ -172,8 +178,8 @@ def wsweep(args):
     out = []
     for n in sorted(sizes):
         xd = xd_all[:n]
-        data = F.make_data(xd, "cosine")
-        params = F.make_params(w.T, w.ef_h, w.R, w.alpha, w.B)
+        data = F.make_data(xd, metric)
+        params = F.make_params(w.T, w.ef_h, w.R, w.alpha, w.B, beam_table_slots=table)
         ws = F.alloc_workspace(data, params)
         u32 = lambda *sh: torch.full(sh, -1, dtype=torch.int32, device="cuda")  # noqa: E731
         G = F.make_graph(u32(n, w.R), u32(n), u32(n), u32(w.T), w.T)
@@ -192,7 +198,8 @@ def wsweep(args):
         del ws, G
         S, R = 2048, 64
         pairs = sum(min(S, n - l0) ** 2 for l0 in range(0, n, S))
-        dl2 = F.make_data(xd, "l2")
+        xf = xd if xd.dtype == torch.float32 else xd.float()
+        dl2 = F.make_data(xf, "l2")
         oi = torch.empty(n, R, dtype=torch.int32, device="cuda")
         od = torch.empty(n, R, dtype=torch.float32, device="cuda")
         for bf16 in (False, True):
@@ -211,7 +218,7 @@ def wsweep(args):
             del lws
         log(f"[wsweep] {json.dumps(rec)}")
         out.append(rec)
-        del oi, od, data, dl2
+        del oi, od, data, dl2, xf
         torch.cuda.empty_cache()
     base = out[0]["harvest_G_evals_per_s"]
     print(json.dumps({"mode": "wsweep", "workload": w.name, "row_bytes": row_bytes, "rows": out,
@@ -538,6 +545,8 @@ def main():
     ap.add_argument("--workloads", default="cfg3,cfg4", help="screen mode: cfg3, cfg4 or both")
     ap.add_argument("--reps", type=int, default=3, help="screen mode: paired repetitions; wsweep: timed builds per prefix")
     ap.add_argument("--sizes", default="", help="wsweep mode: comma-separated prefix sizes")
+    ap.add_argument("--sweep-workload", default="glove", choices=("glove", "u8"),
+                    help="wsweep mode: the GloVe-shaped float32 rows or the benchmark line's uint8 rows")
     ap.add_argument("--arms", default="8:8:128,8:1:128,8:32:128,16:8:128",
                     help="quality mode: comma-separated T:B:ef_h arms (the first is the reference)")
     ap.add_argument("--forms", default="", help="screen mode: fg_screen values to compare with float32 "
