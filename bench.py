@@ -163,10 +163,13 @@ def wsweep(args):
     the larger ones.  With --sweep-workload u8 the same over the 128-byte
     uint8 rows of the benchmark line's workload (T=8 B=8 ef_h=64 R=32, its
     1024-slot visited table), 250,000 to 4,000,000 rows (32 to 512 MB), the
-    blocked kernel on a float32 copy of the rows."""
-    w = gen.CFG2 if args.sweep_workload == "u8" else gen.CFG3
-    default = [250_000, 500_000, 1_000_000, 2_000_000, 4_000_000] if w is gen.CFG2 else \
-        [20_000, 50_000, 100_000, 200_000, 500_000, w.n]
+    blocked kernel on a float32 copy of the rows.  With --sweep-workload gist
+    the GIST-shaped float32 rows (d = 960, 3840 B, T=8 B=8 ef_h=128 R=64),
+    25,000 to 1,000,000 rows (96 MB to 3.8 GB)."""
+    w = {"u8": gen.CFG2, "gist": gen.CFG4}.get(args.sweep_workload, gen.CFG3)
+    default = {id(gen.CFG2): [250_000, 500_000, 1_000_000, 2_000_000, 4_000_000],
+               id(gen.CFG4): [25_000, 50_000, 100_000, 200_000, 500_000, 1_000_000]}.get(
+        id(w), [20_000, 50_000, 100_000, 200_000, 500_000, w.n])
     sizes = [int(v) for v in args.sizes.split(",")] if args.sizes else default
     metric = "cosine" if w.metric == "cosine" else "l2"
     table = 1024 if w is gen.CFG2 else 0
@@ -545,8 +548,9 @@ def main():
     ap.add_argument("--workloads", default="cfg3,cfg4", help="screen mode: cfg3, cfg4 or both")
     ap.add_argument("--reps", type=int, default=3, help="screen mode: paired repetitions; wsweep: timed builds per prefix")
     ap.add_argument("--sizes", default="", help="wsweep mode: comma-separated prefix sizes")
-    ap.add_argument("--sweep-workload", default="glove", choices=("glove", "u8"),
-                    help="wsweep mode: the GloVe-shaped float32 rows or the benchmark line's uint8 rows")
+    ap.add_argument("--sweep-workload", default="glove", choices=("glove", "u8", "gist"),
+                    help="wsweep mode: the GloVe-shaped float32 rows, the benchmark line's uint8 rows "
+                         "or the GIST-shaped float32 rows")
     ap.add_argument("--arms", default="8:8:128,8:1:128,8:32:128,16:8:128",
                     help="quality mode: comma-separated T:B:ef_h arms (the first is the reference)")
     ap.add_argument("--forms", default="", help="screen mode: fg_screen values to compare with float32 "
