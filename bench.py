@@ -307,8 +307,10 @@ def quality(args):
     """The quality columns of Tab. 2 for arms of T (trees) and B (blocks) on
     the GloVe-shaped workload: build time and evaluations, local
     completeness, the recall@10 ladder with distances and queries per second
-    at each beam width, and d@0.95 / d@0.97 against the first arm."""
-    w = gen.CFG3
+    at each beam width, and d@0.95 / d@0.97 against the first arm.  With
+    --quality-workload gist the same on the GIST-shaped rows (d = 960, L2,
+    1,000 held-out queries)."""
+    w = gen.CFG4 if args.quality_workload == "gist" else gen.CFG3
     n = args.n or w.n
     metric = "cosine" if w.metric == "cosine" else "l2"
     arms = [tuple(int(v) for v in a.split(":")) for a in args.arms.split(",")]
@@ -551,6 +553,8 @@ def main():
     ap.add_argument("--sweep-workload", default="glove", choices=("glove", "u8", "gist"),
                     help="wsweep mode: the GloVe-shaped float32 rows, the benchmark line's uint8 rows "
                          "or the GIST-shaped float32 rows")
+    ap.add_argument("--quality-workload", default="glove", choices=("glove", "gist"),
+                    help="quality mode: the GloVe-shaped or the GIST-shaped rows")
     ap.add_argument("--arms", default="8:8:128,8:1:128,8:32:128,16:8:128",
                     help="quality mode: comma-separated T:B:ef_h arms (the first is the reference)")
     ap.add_argument("--forms", default="", help="screen mode: fg_screen values to compare with float32 "
