@@ -303,6 +303,35 @@ def completeness(x: torch.Tensor, nbrs: np.ndarray, cnt: np.ndarray, metric: str
     return hit / (k * len(sample))
 
 
+def coherent_blocks(parent: np.ndarray, cap: int = 512) -> np.ndarray:
+    """Sizes of the coherent blocks of Sec. 5.5: the maximal subtrees of the
+    tree-0 spine (parent[v], 0xFFFFFFFF at the root) holding at most `cap`
+    points, i.e. subtrees of at most cap points whose parent's subtree is
+    larger (or that are the whole tree)."""
+    n = len(parent)
+    par = parent.astype(np.int64)
+    par[parent == 0xFFFFFFFF] = -1
+    roots = np.flatnonzero(par < 0)
+    # breadth-first order from the root(s): children grouped by parent
+    kids = np.argsort(np.where(par < 0, n, par), kind="stable")
+    cnt = np.bincount(par[par >= 0], minlength=n)
+    start = np.concatenate([[0], np.cumsum(cnt)])
+    order = list(roots)
+    i = 0
+    while i < len(order):
+        v = order[i]
+        order.extend(kids[start[v]:start[v + 1]].tolist())
+        i += 1
+    if len(order) != n:
+        raise ValueError("the spine is not a forest over every point")
+    size = np.ones(n, dtype=np.int64)
+    for v in reversed(order):
+        if par[v] >= 0:
+            size[par[v]] += size[v]
+    top = np.where(par >= 0, size[np.maximum(par, 0)], cap + 1)
+    return size[(size <= cap) & (top > cap)]
+
+
 def quality(args):
     """The quality columns of Tab. 2 for arms of T (trees) and B (blocks) on
     the GloVe-shaped workload: build time and evaluations, local
@@ -337,6 +366,10 @@ def quality(args):
                "hash": hex(F.graph_hash(G))}
         nb, cn = G._keep[0].cpu().numpy().view(np.uint32), G._keep[1].cpu().numpy().view(np.uint32)
         rec["completeness"] = completeness(xd, nb, cn, metric, sample)
+        cb = coherent_blocks(G._keep[2].cpu().numpy().view(np.uint32))
+        rec["coherent_blocks"] = {"count": int(len(cb)), "median": float(np.median(cb)),
+                                  "p10": float(np.percentile(cb, 10)), "p90": float(np.percentile(cb, 90)),
+                                  "points_covered": float(cb.sum() / n)}
         ladder = []
         oi = torch.empty(nq, 10, dtype=torch.int32, device="cuda")
         od = torch.empty(nq, 10, dtype=torch.float32, device="cuda")
