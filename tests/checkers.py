@@ -232,3 +232,97 @@ def knn_exact(x: np.ndarray, q: np.ndarray, k: int, metric: str = "l2"):
         d = (qf * qf).sum(1)[:, None] + (xf * xf).sum(1)[None, :] - 2 * qf @ xf.T
     idx = np.lexsort((np.broadcast_to(np.arange(x.shape[0]), d.shape), d), axis=1)[:, :k]
     return idx, np.take_along_axis(d, idx, 1)
+
+
+# --------------------------------------------------------------------------
+# Work counts (Sec. 2: every distance evaluation counts), restated from the
+# finished structures that the characterisations above pin, per candidate
+# rather than by replaying the loops that produced them.
+# --------------------------------------------------------------------------
+
+def prune_pair_count(DM_p: dict, DM: np.ndarray, cand: list, kept: list, R: int, alpha: float) -> int:
+    """Pair distances of the lazy greedy prune, from its kept list: the
+    kept candidates test later live ones, except the R-th kept, after which
+    the prune stops.  So each candidate c is tested by the testing kept
+    candidates ranked before it, in rank order, up to and including the first
+    one whose float32-scaled distance reaches d(p, c) (that one kills it)."""
+    key = lambda c: (DM_p[c], c)  # noqa: E731
+    C = sorted(set(int(c) for c in cand), key=key)
+    rank = {c: i for i, c in enumerate(C)}
+    kept = [int(k) for k in kept]
+    testers = kept[:-1] if len(kept) == R else kept
+    total = 0
+    for c in C:
+        for a in testers:
+            if rank[a] >= rank[c]:
+                break
+            total += 1
+            if f32_mul(alpha, DM[a, c]) <= DM_p[c]:
+                break
+    return total
+
+
+def sat_eval_count(DM: np.ndarray, root: int, parent: np.ndarray) -> int:
+    """Distance evaluations of the classic SAT construction, from the tree:
+    at every node a with descendants S and children N ranked by (d(v,a), v),
+    |S| distances to a; each v of S is tested against the children ranked
+    before it, in that order, up to and including the first b with
+    d(v,b) <= d(v,a) (all of them when v is a child); and each descendant
+    that is not a child takes its distance to every child (closest-child
+    assignment)."""
+    n = DM.shape[0]
+    children = [[] for _ in range(n)]
+    for v in range(n):
+        if v != root:
+            children[int(parent[v])].append(v)
+    desc = [None] * n
+    order, stack = [], [root]
+    while stack:
+        a = stack.pop()
+        order.append(a)
+        stack.extend(children[a])
+    for a in reversed(order):
+        s = set()
+        for c in children[a]:
+            s.add(c)
+            s |= desc[c]
+        desc[a] = s
+    total = 0
+    for a in range(n):
+        S = desc[a]
+        if not S:
+            continue
+        ranked = sorted(S, key=lambda v: (DM[v, a], v))
+        rank = {v: r for r, v in enumerate(ranked)}
+        N = sorted(children[a], key=lambda v: rank[v])
+        Nset = set(N)
+        total += len(S)
+        for v in S:
+            for b in N:
+                if rank[b] >= rank[v]:
+                    break
+                total += 1
+                if DM[v, b] <= DM[v, a]:
+                    break
+        total += (len(S) - len(N)) * len(N)
+    return total
+
+
+def finalize_eval_count(DM: np.ndarray, rows: np.ndarray, cnt: np.ndarray, g: np.ndarray, gc: np.ndarray,
+                        R: int, alpha: float, reprune_all: bool = False) -> int:
+    """Finalize's distance evaluations, from its input rows and output graph:
+    one distance per distinct symmetrised candidate of every point, plus the
+    prune's pair count (from the point's output row) where the candidates
+    exceed R or every row is re-pruned."""
+    n = rows.shape[0]
+    cand = [set(int(u) for u in rows[p, :cnt[p]]) for p in range(n)]
+    for u in range(n):
+        for v in rows[u, :cnt[u]]:
+            cand[int(v)].add(u)
+    total = 0
+    for p in range(n):
+        C = sorted(cand[p])
+        total += len(C)
+        if len(C) > R or reprune_all:
+            total += prune_pair_count({c: DM[p, c] for c in C}, DM, C, g[p, :gc[p]].tolist(), R, alpha)
+    return total
