@@ -263,6 +263,28 @@ fg_status fg_search(const fg_data* data, const fg_graph* graph,
                     uint32_t* out_evals_dev, void* ws_dev, size_t ws_bytes,
                     void* stream);
 
+/* fg_search for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results and errors as fg_search, without a workspace: the
+ * kernels' scratch (a control block, the G u spine CSR, per-search visited
+ * bitsets) lives in a fixed array of fg_search_noalloc_scratch_bytes()
+ * bytes (64 MiB) that the library holds on each GPU it runs on until the
+ * process ends.  The call allocates nothing and does not synchronise; its
+ * device address is looked up on the first call on each device.
+ * Limit: 4096 + 8 (n + 1) + 4 (R n + 2 n + 1) + 4 n bytes (each rounded up
+ * to 256) plus, for at least one search per compute unit, 4 ceil(n / 32) +
+ * 8192 bytes per search must fit; otherwise FG_EINVAL with a message and
+ * nothing enqueued (n = 100,000 with R = 64 fits).  Every call on one GPU
+ * uses that GPU's one array: calls that overlap in time on the same GPU
+ * (other streams, other threads) race and give wrong results.  Each call
+ * clears what must start at zero on `stream` itself. */
+size_t fg_search_noalloc_scratch_bytes(void);
+fg_status fg_search_noalloc(const fg_data* data, const fg_graph* graph,
+                            const void* queries_dev, int64_t nq, uint32_t k,
+                            uint32_t L, uint32_t* out_ids_dev,
+                            void* out_dists_dev, uint32_t* out_evals_dev,
+                            void* stream);
+
 /* FNV-1a-64 over the graph's little-endian byte image: n (u64), R, T (u32),
  * then per point its count and ids, then the spine parents, then the roots.
  * Copies the graph to the host; synchronises `stream`. */

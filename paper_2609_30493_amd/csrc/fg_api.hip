@@ -478,6 +478,58 @@ uint64_t splitmix64(uint64_t seed, uint64_t k) {
 }
 
 }  // namespace
+
+fg_status check_search(const fg_data* data, const fg_graph* graph, const void* queries_dev, int64_t nq, uint32_t k,
+                       uint32_t L, const uint32_t* out_ids_dev, const void* out_dists_dev, Shape* s) {
+  if (!make_shape(data, s)) return FG_EINVAL;
+  if (!graph || !graph->nbrs_dev || !graph->cnt_dev || !graph->spine_parent_dev || !graph->roots_dev ||
+      graph->n != s->n || graph->T < 1 || graph->T > 64 || graph->R < 1)
+    return set_error("graph is incomplete or does not match the data"), FG_EINVAL;
+  if (!queries_dev || nq < 0 || !out_ids_dev || !out_dists_dev)
+    return set_error("queries and outputs are required"), FG_EINVAL;
+  if (reinterpret_cast<uintptr_t>(queries_dev) % 16) return set_error("queries must be 16-byte aligned"), FG_EINVAL;
+  if (k < 1 || L < k || L > (uint32_t)kMaxEfSearch) return set_error("need 1 <= k <= L <= 512"), FG_EINVAL;
+  return FG_OK;
+}
+
+fg_status search_run(const Shape& s, const fg_graph* graph, const void* queries_dev, int64_t nq, uint32_t k,
+                     uint32_t L, uint32_t* out_ids, void* out_d, uint32_t* out_evals, const SearchScratch& w,
+                     int grid, hipStream_t st) {
+  Ctl* ctl = static_cast<Ctl*>(w.ctl);
+  FG_HIP(fill_u64(reinterpret_cast<uint64_t*>(ctl), 0, 4096 / 8, st));
+  FG_HIP(search_graph(s.n, (int)graph->R, graph->nbrs_dev, graph->cnt_dev, graph->spine_parent_dev, w.deg,
+                      w.sgoff, w.sgids, w.scan, st));
+  FG_HIP(fill_u32(w.bits, 0, (int64_t)grid * w.spill_words, st));
+  BeamArgs a{};
+  a.x = s.x;
+  a.stride = s.stride;
+  a.n = s.n;
+  a.Q = s.Q;
+  a.off = w.sgoff;
+  a.ids = w.sgids;
+  a.roots = graph->roots_dev;
+  a.T = (int)graph->T;
+  a.ef = (int)L;
+  a.queries = static_cast<const uint8_t*>(queries_dev);
+  a.qstride = (int64_t)s.d * (s.dk == U8L2 ? 1 : 4);
+  a.k = (int)k;
+  a.out_ids = out_ids;
+  a.out_d = out_d;
+  a.out_evals = out_evals;
+  a.nitems = nq;
+  a.queue = &ctl->queue;
+  a.Ebuf = nullptr;  // a search keeps no expanded list
+  a.Ecap = 0;
+  a.spill_bits = w.bits;
+  a.spill_words = w.spill_words;
+  a.spill_list = w.slist;
+  a.spill_cap = w.spill_cap;
+  a.counters = ctl->counters;
+  a.status = &ctl->status;
+  FG_HIP(launch_beam(s, a, true, grid, 4096, st));
+  return FG_OK;
+}
+
 }  // namespace fg
 
 using namespace fg;
@@ -710,14 +762,8 @@ fg_status fg_search(const fg_data* data, const fg_graph* graph, const void* quer
                     uint32_t k, uint32_t L, uint32_t* out_ids_dev, void* out_dists_dev,
                     uint32_t* out_evals_dev, void* ws_dev, size_t ws_bytes, void* stream) {
   Shape s;
-  if (!make_shape(data, &s)) return FG_EINVAL;
-  if (!graph || !graph->nbrs_dev || !graph->cnt_dev || !graph->spine_parent_dev || !graph->roots_dev ||
-      graph->n != s.n || graph->T < 1 || graph->T > 64 || graph->R < 1)
-    return set_error("graph is incomplete or does not match the data"), FG_EINVAL;
-  if (!queries_dev || nq < 0 || !out_ids_dev || !out_dists_dev)
-    return set_error("queries and outputs are required"), FG_EINVAL;
-  if (reinterpret_cast<uintptr_t>(queries_dev) % 16) return set_error("queries must be 16-byte aligned"), FG_EINVAL;
-  if (k < 1 || L < k || L > (uint32_t)kMaxEfSearch) return set_error("need 1 <= k <= L <= 512"), FG_EINVAL;
+  fg_status r = check_search(data, graph, queries_dev, nq, k, L, out_ids_dev, out_dists_dev, &s);
+  if (r) return r;
   fg_params P{};
   P.T = graph->T;
   P.R = graph->R;
@@ -726,45 +772,20 @@ fg_status fg_search(const fg_data* data, const fg_graph* graph, const void* quer
   WsMap m = ws_map(s.n, &P);
   if (!check_ws(ws_dev, ws_bytes, m)) return FG_ENOMEM;
   if (nq == 0) return FG_OK;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  fg_status r = reset_ctl(ws_dev, m, st);
-  if (r) return r;
-  uint64_t* sgoff = reinterpret_cast<uint64_t*>(at(ws_dev, m.sgoff));
-  uint32_t* sgids = reinterpret_cast<uint32_t*>(at(ws_dev, m.sgids));
-  FG_HIP(search_graph(s.n, (int)graph->R, graph->nbrs_dev, graph->cnt_dev, graph->spine_parent_dev,
-                      reinterpret_cast<uint32_t*>(at(ws_dev, m.deg)), sgoff, sgids, at(ws_dev, m.scan), st));
-  FG_HIP(fill_u32(reinterpret_cast<uint32_t*>(at(ws_dev, m.bits)), 0, (int64_t)kMaxWaveSlots * m.spill_words, st));
   int grid = beam_grid(s, (int)L, true, 4096);
   if (grid <= 0) return set_error("no search kernel for this row size / L"), FG_EUNSUPPORTED;
-  Ctl* ctl = reinterpret_cast<Ctl*>(at(ws_dev, m.ctl));
-  BeamArgs a{};
-  a.x = s.x;
-  a.stride = s.stride;
-  a.n = s.n;
-  a.Q = s.Q;
-  a.off = sgoff;
-  a.ids = sgids;
-  a.roots = graph->roots_dev;
-  a.T = (int)graph->T;
-  a.ef = (int)L;
-  a.queries = static_cast<const uint8_t*>(queries_dev);
-  a.qstride = (int64_t)s.d * (data->dtype == FG_F32 ? 4 : 1);
-  a.k = (int)k;
-  a.out_ids = out_ids_dev;
-  a.out_d = out_dists_dev;
-  a.out_evals = out_evals_dev;
-  a.nitems = nq;
-  a.queue = &ctl->queue;
-  a.Ebuf = reinterpret_cast<uint64_t*>(at(ws_dev, m.ebuf));
-  a.Ecap = kEcap;
-  a.spill_bits = reinterpret_cast<uint32_t*>(at(ws_dev, m.bits));
-  a.spill_words = m.spill_words;
-  a.spill_list = reinterpret_cast<uint32_t*>(at(ws_dev, m.slist));
-  a.spill_cap = kSpillCap;
-  a.counters = ctl->counters;
-  a.status = &ctl->status;
-  FG_HIP(launch_beam(s, a, true, grid, 4096, st));
-  return FG_OK;
+  SearchScratch w{};
+  w.ctl = at(ws_dev, m.ctl);
+  w.sgoff = reinterpret_cast<uint64_t*>(at(ws_dev, m.sgoff));
+  w.sgids = reinterpret_cast<uint32_t*>(at(ws_dev, m.sgids));
+  w.deg = reinterpret_cast<uint32_t*>(at(ws_dev, m.deg));
+  w.scan = at(ws_dev, m.scan);
+  w.bits = reinterpret_cast<uint32_t*>(at(ws_dev, m.bits));
+  w.spill_words = m.spill_words;
+  w.slist = reinterpret_cast<uint32_t*>(at(ws_dev, m.slist));
+  w.spill_cap = kSpillCap;
+  return search_run(s, graph, queries_dev, nq, k, L, out_ids_dev, out_dists_dev, out_evals_dev, w, grid,
+                    static_cast<hipStream_t>(stream));
 }
 
 fg_status fg_graph_hash(const fg_graph* graph, void* stream, uint64_t* out) {

@@ -153,6 +153,30 @@ struct FinalizeBig {
 };
 hipError_t launch_finalize(int dk, int Q, const FinalizeArgs& a, const FinalizeBig& big, hipStream_t st);
 
+// Query search (fg_api.hip), shared by fg_search and fg_search_noalloc.
+// Its device scratch: a 4096-byte control block (queue, counters, status),
+// the G u spine CSR (n + 1 offsets, R n + 2 n + 1 ids), n degree words, the
+// scan's scratch, `grid` visited bitsets of spill_words words each and
+// `grid` spill lists of spill_cap ids each.
+struct SearchScratch {
+  void* ctl;
+  uint64_t* sgoff;
+  uint32_t* sgids;
+  uint32_t* deg;
+  void* scan;
+  uint32_t* bits;
+  int64_t spill_words;
+  uint32_t* slist;
+  int spill_cap;
+};
+fg_status check_search(const fg_data* data, const fg_graph* graph, const void* queries_dev, int64_t nq, uint32_t k,
+                       uint32_t L, const uint32_t* out_ids_dev, const void* out_dists_dev, Shape* s);
+// Clears the control block and the first `grid` bitsets, builds the CSR and
+// launches the search kernel with `grid` wave slots.  Asynchronous.
+fg_status search_run(const Shape& s, const fg_graph* graph, const void* queries_dev, int64_t nq, uint32_t k,
+                     uint32_t L, uint32_t* out_ids, void* out_d, uint32_t* out_evals, const SearchScratch& w,
+                     int grid, hipStream_t st);
+
 // Leaf k-NN on MFMA (fg_dense.hip).
 size_t leaf_knn_ws_bytes(int64_t n, int d);
 hipError_t leaf_knn(const Shape& s, int S, int R, bool bf16, void* ws, uint32_t* out_ids, float* out_d,

@@ -90,6 +90,8 @@ _SIGS = {
     "fg_build_graph": (C.c_int, [P, C.c_uint64, P, P, P, C.c_size_t, P, P, P]),
     "fg_search": (C.c_int, [P, P, P, C.c_int64, C.c_uint32, C.c_uint32, P, P, P, P,
                             C.c_size_t, P]),
+    "fg_search_noalloc": (C.c_int, [P, P, P, C.c_int64, C.c_uint32, C.c_uint32, P, P, P, P]),
+    "fg_search_noalloc_scratch_bytes": (C.c_size_t, []),
     "fg_graph_hash": (C.c_int, [P, P, P]),
     "fg_sync_status": (C.c_int, [P, P]),
     "fg_autotune": (C.c_int, [P, P, C.c_char_p, P, C.c_size_t, P, P]),
@@ -260,6 +262,17 @@ def search(data: fg_data, graph: fg_graph, queries: torch.Tensor, k: int, L: int
     _check(lib().fg_search(C.byref(data), C.byref(graph), _ptr(queries), queries.shape[0], k,
                            L, _ptr(out_ids), _ptr(out_d), _ptr(out_evals), wp, wn,
                            _stream(stream)))
+
+
+def search_noalloc(data: fg_data, graph: fg_graph, queries: torch.Tensor, k: int, L: int,
+                   out_ids, out_d, out_evals, stream=None):
+    """fg_search without a workspace (the library's fixed per-GPU scratch)."""
+    _check(lib().fg_search_noalloc(C.byref(data), C.byref(graph), _ptr(queries), queries.shape[0], k,
+                                   L, _ptr(out_ids), _ptr(out_d), _ptr(out_evals), _stream(stream)))
+
+
+def search_noalloc_scratch_bytes() -> int:
+    return int(lib().fg_search_noalloc_scratch_bytes())
 
 
 def autotune(data: fg_data, params: fg_params, ws, cache_path=None, stream=None) -> fg_params:
