@@ -94,15 +94,26 @@ typedef struct {
  * (frozen Graft).  reprune_all = 0 re-prunes in finalize only the rows whose
  * symmetrised candidate set exceeds R; 1 re-prunes every row.
  * beam_table_slots is a tuning knob that never changes the graph: the size
- * of each harvest search's on-chip visited table, 1024, 2048 or 4096 (0 =
- * 4096 for FG_F32 rows of more than 256 elements, else 2048 when
- * ef_h <= 128 and 4096 otherwise; ef_h > 128 always uses 4096; 1024
- * applies to ef_h <= 64 with rows of at most 256 bytes, else 2048 is used).
- * Smaller tables let more searches run per compute unit.  A search whose
- * expanded set exceeds half the table size fails with FG_ECAPACITY.
+ * of each harvest search's on-chip visited table, 512, 1024, 2048 or 4096
+ * (0 = 4096 for FG_F32 rows of more than 256 elements, else 2048 when
+ * ef_h <= 128 and 4096 otherwise; ef_h > 128 always uses 4096; 512 and
+ * 1024 apply to the unscreened harvest with ef_h <= 128 and the library's
+ * lanes per row, else 2048 is used).  Smaller tables let more searches run
+ * per compute unit; a search whose visits outgrow its table continues in a
+ * device bitset.  A search's
+ * expanded set is sorted and pruned on chip up to half the table's slots and
+ * in the workspace beyond; a search that expands 8192 vertices or more fails
+ * the call with FG_ECAPACITY (Sec. 3 bounds nothing: the bound is this
+ * library's).
  * screen is an fg_screen; it never changes the graph either.  waves_per_cu
  * caps the resident harvest searches per compute unit (0 = as many as fit);
- * another knob that never changes the graph (see fg_autotune). */
+ * another knob that never changes the graph (see fg_autotune).  So is
+ * lanes_per_row: how many lanes of a wave share one row's gather in the
+ * plain harvest (0 = the library's choice: 8 for rows of at most 128
+ * bytes, else 16; 4 for rows of at most 128 bytes and 8 for rows of
+ * 129..512 bytes hold more rows in flight; any other combination uses the
+ * library's choice).  The declared summation order gives the same bits for
+ * every lane count. */
 typedef struct {
   uint32_t T;
   uint32_t ef_h;
@@ -113,7 +124,7 @@ typedef struct {
   uint32_t beam_table_slots;
   uint32_t screen;
   uint32_t waves_per_cu;
-  uint32_t reserved;
+  uint32_t lanes_per_row;
 } fg_params;
 
 /* Compressed rows in device memory: row v is ids_dev[off_dev[v] ..
@@ -231,18 +242,55 @@ fg_status fg_build_graph(const fg_data* data, uint64_t seed,
                          size_t ws_bytes, void* stream, fg_counters* counters,
                          fg_timings* timings);
 
+/* Visit log of the harvest searches, for the lockstep-density measurement
+ * (Sec. 5.5, Tab. 6: the density of a block of points is the sum of their
+ * visited-set sizes over the block size times the size of the union).
+ * slot_dev (n entries, device) selects the points: slot_dev[p] in
+ * [0, nslots) logs p's own harvest search (in block p mod max(B,1), over
+ * S_b) into that slot; any other value logs nothing.  Per slot: ids_dev[slot
+ * * cap ..] receives the ids the search visits, in visit order (the roots in
+ * order, then each expanded row's unvisited ids in row order), the first cap
+ * of them; len_dev[slot] the total; marks_dev[slot * FG_LOG_MARKS + e] the
+ * visit count after the roots (e = 0) and after expansion e (e = 1..16; after
+ * the search's last expansion, its total).  Two points must not share a
+ * slot.  All device memory, caller-owned. */
+#define FG_LOG_MARKS 17
+typedef struct {
+  const int32_t* slot_dev;
+  uint32_t nslots;
+  uint32_t cap;
+  uint32_t* ids_dev;
+  uint32_t* len_dev;
+  uint32_t* marks_dev;
+} fg_visit_log;
+
+/* fg_build_graph that also fills a visit log (the same graph, counters and
+ * timings; its harvest always uses the 4096-slot visited table).  screen
+ * must be FG_SCREEN_NONE (FG_EUNSUPPORTED otherwise). */
+fg_status fg_build_graph_log(const fg_data* data, uint64_t seed,
+                             const fg_params* params, fg_graph* out,
+                             void* ws_dev, size_t ws_bytes, void* stream,
+                             fg_counters* counters, fg_timings* timings,
+                             const fg_visit_log* log);
+
 /* Batched builds: count independent instances, each exactly the graph
  * fg_build_graph would give it (same hash), built together so that one
  * harvest launch per block serves every instance (uneven beam lengths and
  * small instances keep the whole device busy).  Instances share dtype,
- * metric, T, R, alpha, B, reprune_all and beam_table_slots; n, d, ef_h and
- * the seed may differ; screen must be FG_SCREEN_NONE.  outs[i] is shaped
- * like instance i.  With use_hipgraph != 0 the B harvests and merges are
- * captured into one HIP graph (on a stream of the library's own, ordered
- * after and before `stream`) and replayed once; merges then finish rows
- * with more than 2048 additions on the device alone.  Synchronises
- * `stream`.  The workspace must hold
+ * metric, T, R, alpha, B, reprune_all and the tuning knobs of params[0]; n,
+ * d, ef_h and the seed may differ; screen must be FG_SCREEN_NONE.  outs[i]
+ * is shaped like instance i.  flags: FG_BATCH_HIPGRAPH captures the B
+ * harvests and merges into one HIP graph (on a stream of the library's own,
+ * ordered after and before `stream`) and replays it once; merges then
+ * finish rows with more than 2048 additions on the device alone.
+ * FG_BATCH_AUTOTUNE replaces params[0]'s lanes_per_row, beam_table_slots
+ * and waves_per_cu by the fastest candidates timed on this batch's own
+ * harvest launch (block 0 of every instance over S_0, best of two; the
+ * choice is kept per batch shape in host memory for later calls); no
+ * graph changes.  Synchronises `stream`.  The workspace must hold
  * fg_batched_workspace_size() bytes (0 = invalid arguments). */
+#define FG_BATCH_HIPGRAPH 1
+#define FG_BATCH_AUTOTUNE 2
 size_t fg_batched_workspace_size(const fg_data* const* data,
                                  const fg_params* const* params, uint32_t count);
 fg_status fg_build_graph_batched(const fg_data* const* data,
@@ -250,7 +298,7 @@ fg_status fg_build_graph_batched(const fg_data* const* data,
                                  const uint64_t* seeds, uint32_t count,
                                  fg_graph* const* outs, void* ws_dev,
                                  size_t ws_bytes, void* stream,
-                                 int use_hipgraph, fg_counters* counters);
+                                 int flags, fg_counters* counters);
 
 /* Query search (Sec. 2, "quality"): beam of width L over G u spine from the
  * roots for nq query rows (queries_dev, contiguous rows of d elements of the
@@ -311,10 +359,10 @@ fg_status fg_leaf_knn(const fg_data* data, uint32_t leaf_size, uint32_t R,
  * the data's element order, rows fg_screen_row_bytes(d, screen) bytes apart
  * (bfloat16: 2d rounded up to a multiple of 32, pad bytes written as zero;
  * fp8: d rounded up to a multiple of 16, pad bytes not written).
- * err_dev[i] >= |x^_i - x_i| and norm_dev[i] >= |x_i| (float64 sums rounded
- * up), sinv_dev[i] = 2^-k (1 for bfloat16), where x^_i is the copy read
- * back (fp8: code * 2^-k).  FG_F32 data with d > 64 only.  Asynchronous on
- * `stream`. */
+ * err_dev[i] >= |x^_i - x_i| and norm_dev[i] >= |x_i| (float32 sums of
+ * scaled squares raised by their rounding bound), sinv_dev[i] = 2^-k (1 for
+ * bfloat16), where x^_i is the copy read back (fp8: code * 2^-k).  FG_F32
+ * data with d > 64 only.  Asynchronous on `stream`. */
 int64_t fg_screen_row_bytes(int32_t d, uint32_t screen);
 fg_status fg_screen_copy(const fg_data* data, uint32_t screen, void* xs_dev,
                          float* err_dev, float* norm_dev, float* sinv_dev,
@@ -322,11 +370,12 @@ fg_status fg_screen_copy(const fg_data* data, uint32_t screen, void* xs_dev,
 
 /* Autotuning of the harvest's knobs (none changes the graph): the
  * visited-table size (beam_table_slots 1024 / 2048 / 4096, where ef_h and
- * the row size allow) and
- * the resident searches per compute unit (waves_per_cu).  On the first
+ * the row size allow), the resident searches per compute unit
+ * (waves_per_cu) and the lanes that share one row (lanes_per_row: the
+ * library's shape and the other one where it exists).  On the first
  * min(n, 50000) rows it builds a scaffold, then times block 0's harvest
  * for each candidate (best of two) and writes the fastest into *tuned (a
- * copy of *params with those two fields set).  With cache_path != NULL the
+ * copy of *params with those three fields set).  With cache_path != NULL the
  * result is looked up in / appended to that text file, one line per
  * (dtype, metric, row chunks, ef_h, R, T, B, log2 n).  The workspace is the
  * one fg_workspace_size gives for data and params.  Synchronises `stream`. */

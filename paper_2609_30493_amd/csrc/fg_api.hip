@@ -3,6 +3,9 @@
 #include <math.h>
 #include <string.h>
 
+#include <array>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -60,11 +63,13 @@ bool check_params(const fg_params* p, int64_t n, bool need_ef = true) {
     return set_error("need 1 <= ef_h <= 256"), false;
   if (p->R < 1 || p->R > 1024) return set_error("need 1 <= R <= 1024"), false;
   if (!isfinite(p->alpha) || p->alpha < 1.0f) return set_error("alpha must be finite and >= 1"), false;
-  if (p->beam_table_slots != 0 && p->beam_table_slots != 1024 && p->beam_table_slots != 2048 &&
-      p->beam_table_slots != 4096)
-    return set_error("beam_table_slots must be 0, 1024, 2048 or 4096"), false;
+  if (p->beam_table_slots != 0 && p->beam_table_slots != 512 && p->beam_table_slots != 1024 &&
+      p->beam_table_slots != 2048 && p->beam_table_slots != 4096)
+    return set_error("beam_table_slots must be 0, 512, 1024, 2048 or 4096"), false;
   if (p->screen > FG_SCREEN_BF16_PRUNE) return set_error("screen must be an fg_screen"), false;
   if (p->waves_per_cu > 64) return set_error("waves_per_cu must be 0..64"), false;
+  if (p->lanes_per_row != 0 && p->lanes_per_row != 4 && p->lanes_per_row != 8 && p->lanes_per_row != 16)
+    return set_error("lanes_per_row must be 0, 4, 8 or 16"), false;
   return true;
 }
 
@@ -99,7 +104,8 @@ uint32_t b_eff(const fg_params* p) { return p->B > 1 ? p->B : 1; }
 // per SIMD, and the larger table keeps searches off the device bitset
 // (measured 6% faster on the 200,000 x 960 build).
 int table_request(const fg_params* p, int nch = 1) {
-  if (p->beam_table_slots == 1024 || p->beam_table_slots == 2048 || p->beam_table_slots == 4096)
+  if (p->beam_table_slots == 512 || p->beam_table_slots == 1024 || p->beam_table_slots == 2048 ||
+      p->beam_table_slots == 4096)
     return (int)p->beam_table_slots;
   if (nch >= 16) return 4096;
   return p->ef_h <= 128 ? 2048 : 4096;
@@ -122,6 +128,7 @@ struct WsMap {
   size_t rank;                              // each id's position in that order
   size_t gram;                              // Gram-tile prune scratch (float32, d > 256)
   size_t norm;                              // |x_i|^2 per row for it
+  size_t pairs;                             // the substrate's (id, rank) pairs
   int64_t xs_stride;
   SatWs satw;
   size_t total;
@@ -148,7 +155,7 @@ WsMap ws_map(int64_t n, const fg_params* p, int d = 0) {
   m.ctl = take(4096);
   m.bits = take((size_t)kMaxWaveSlots * m.spill_words * 4);
   m.slist = take((size_t)kMaxWaveSlots * kSpillCap * 4);
-  m.ebuf = take((size_t)kMaxWaveSlots * kEcap * 8);
+  m.ebuf = take((size_t)kMaxWaveSlots * (kEcap + kEcap / 64) * 8);
   m.deg = take(un * 4);
   m.cursor = take(un * 4);
   m.newlen = take(un * 4);
@@ -184,6 +191,10 @@ WsMap ws_map(int64_t n, const fg_params* p, int d = 0) {
     m.gram = take((size_t)kGramSlots * kGramMax * kGramMax * 4);
     m.norm = take(un * 4);
   }
+  // rows of 68..256 float32 elements (2..4 chunks per lane) index the
+  // harvest's visited bitsets by rank: the substrate's ids paired with ranks
+  if (p && d >= 68 && d <= 256 && d % 4 == 0) m.pairs = take(m.csr_cap * 8);
+
   if (p && p->screen && d > 0) {
     m.xs_stride = screen_stride(d, copy_kind(p->screen));
     if (search_screen(p->screen) != SCR_NONE) m.xs = take(un * (uint64_t)m.xs_stride);
@@ -244,16 +255,24 @@ fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* id
                          const uint32_t* roots, const fg_params* P, uint32_t b, uint32_t* rows,
                          uint32_t* cnt, void* ws, const WsMap& m, hipStream_t st,
                          const BatchInfo* bi = nullptr, const uint32_t* order = nullptr,
-                         const uint32_t* rank = nullptr) {
+                         const uint32_t* rank = nullptr, const fg_visit_log* log = nullptr) {
   const uint32_t Be = b_eff(P);
   int64_t nitems = s.n > (int64_t)b ? (s.n - (int64_t)b + Be - 1) / Be : 0;
   Ctl* ctl = reinterpret_cast<Ctl*>(at(ws, m.ctl));
   FG_HIP(fill_u64(reinterpret_cast<uint64_t*>(&ctl->queue), 0, 1, st));
   if (nitems == 0) return FG_OK;
   const int ef = bi ? bi->ef_max : (int)P->ef_h;
-  const int hslots = beam_table_slots(ef, false, table_request(P, beam_chunks_per_lane(s)), beam_chunks_per_lane(s));
-  const int screen = search_screen(P->screen);
-  int grid = beam_grid(s, ef, false, hslots, screen, (int)P->waves_per_cu);
+  // the logging kernels exist with the 4096-slot table only, the other
+  // lanes-per-row shapes for the plain harvest only (none of these knobs
+  // changes the graph)
+  const int screen = log ? kBeamLog : search_screen(P->screen);
+  const int lanes = screen == SCR_NONE ? (int)P->lanes_per_row : 0;
+  const int nch = beam_chunks_per_lane(s, lanes);
+  int hslots = log ? 4096 : beam_table_slots(ef, false, table_request(P, nch), nch);
+  // the small tables exist for the plain kernels of the library's shape
+  int Lv = 0, nv = 0;
+  if (hslots < 2048 && (screen != SCR_NONE || lanes_variant(s.dk, s.Q, lanes, &Lv, &nv))) hslots = 2048;
+  int grid = beam_grid(s, ef, false, hslots, screen, (int)P->waves_per_cu, lanes);
   if (grid <= 0) return set_error("no beam kernel for this row size / ef_h"), FG_EUNSUPPORTED;
   BeamArgs a{};
   a.x = s.x;
@@ -274,13 +293,18 @@ fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* id
   a.nitems = nitems;
   a.order = order;
   a.rank = rank;
+  if (rank && m.pairs && !bi && nch >= 2 && nch <= 4 && s.dk != U8L2) {
+    uint2* pairs = reinterpret_cast<uint2*>(at(ws, m.pairs));
+    FG_HIP(csr_rank_pairs(s.n, off, ids, rank, pairs, st));
+    a.idr = pairs;
+  }
   a.queue = &ctl->queue;
   if (order) {
     FG_HIP(fill_u32(ctl->xq, 0, 8, st));
     a.xqueue = ctl->xq;
   }
   a.Ebuf = reinterpret_cast<uint64_t*>(at(ws, m.ebuf));
-  a.Ecap = hslots / 2;  // the expanded set is sorted in the visited table's space
+  a.Ecap = kEcap;
   a.spill_bits = reinterpret_cast<uint32_t*>(at(ws, m.bits));
   a.spill_words = m.spill_words;
   a.spill_list = reinterpret_cast<uint32_t*>(at(ws, m.slist));
@@ -300,14 +324,21 @@ fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* id
     a.inst_ef = bi->inst_ef;
     a.inst_q = bi->inst_q;
   }
-  if (screen) {
+  if (log) {
+    a.log_slot = log->slot_dev;
+    a.log_ids = log->ids_dev;
+    a.log_len = log->len_dev;
+    a.log_marks = log->marks_dev;
+    a.log_cap = log->cap;
+    a.log_nslots = (int)log->nslots;
+  } else if (screen) {
     a.xs = reinterpret_cast<const uint8_t*>(at(ws, m.xs));
     a.xs_stride = m.xs_stride;
     a.xs_err = reinterpret_cast<const float*>(at(ws, m.xs_err));
     a.xs_norm = reinterpret_cast<const float*>(at(ws, m.xs_norm));
     a.xs_sinv = reinterpret_cast<const float*>(at(ws, m.xs_sinv));
   }
-  FG_HIP(launch_beam(s, a, false, grid, hslots, st, screen));
+  FG_HIP(launch_beam(s, a, false, grid, hslots, st, screen, lanes));
   return FG_OK;
 }
 
@@ -469,6 +500,23 @@ fg_status status_error(int status) {
   return FG_OK;
 }
 
+// Tuned knobs of batch shapes already tuned in this process (host memory).
+std::mutex g_tune_mu;
+std::map<std::string, std::array<uint32_t, 3>> g_tuned;
+
+bool tuned_lookup(const std::string& key, uint32_t out[3]) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = g_tuned.find(key);
+  if (it == g_tuned.end()) return false;
+  for (int i = 0; i < 3; i++) out[i] = it->second[i];
+  return true;
+}
+
+void tuned_store(const std::string& key, const uint32_t v[3]) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tuned[key] = {v[0], v[1], v[2]};
+}
+
 uint64_t splitmix64(uint64_t seed, uint64_t k) {
   // Output k of the SplitMix64 stream (Steele, Lea and Flood 2014).
   uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
@@ -478,6 +526,11 @@ uint64_t splitmix64(uint64_t seed, uint64_t k) {
 }
 
 }  // namespace
+
+// The whole build (fg_build_graph, and fg_build_graph_log with a visit log).
+fg_status build_graph_impl(const fg_data* data, uint64_t seed, const fg_params* params, fg_graph* out,
+                           void* ws_dev, size_t ws_bytes, void* stream, fg_counters* counters,
+                           fg_timings* timings, const fg_visit_log* log);
 
 fg_status check_search(const fg_data* data, const fg_graph* graph, const void* queries_dev, int64_t nq, uint32_t k,
                        uint32_t L, const uint32_t* out_ids_dev, const void* out_dists_dev, Shape* s) {
@@ -828,6 +881,28 @@ fg_status fg_graph_hash(const fg_graph* graph, void* stream, uint64_t* out) {
 fg_status fg_build_graph(const fg_data* data, uint64_t seed, const fg_params* params, fg_graph* out,
                          void* ws_dev, size_t ws_bytes, void* stream, fg_counters* counters,
                          fg_timings* timings) {
+  return build_graph_impl(data, seed, params, out, ws_dev, ws_bytes, stream, counters, timings, nullptr);
+}
+
+fg_status fg_build_graph_log(const fg_data* data, uint64_t seed, const fg_params* params, fg_graph* out,
+                             void* ws_dev, size_t ws_bytes, void* stream, fg_counters* counters,
+                             fg_timings* timings, const fg_visit_log* log) {
+  if (!log || !log->slot_dev || !log->ids_dev || !log->len_dev || !log->marks_dev || log->nslots < 1 ||
+      log->cap < 1 || log->nslots > (uint32_t)INT32_MAX)
+    return set_error("fg_visit_log: slot, ids, len and marks arrays, nslots >= 1 and cap >= 1 are required"),
+           FG_EINVAL;
+  if (!params || params->screen != FG_SCREEN_NONE)
+    return set_error("the visit log records the unscreened harvest (screen must be FG_SCREEN_NONE)"),
+           FG_EUNSUPPORTED;
+  return build_graph_impl(data, seed, params, out, ws_dev, ws_bytes, stream, counters, timings, log);
+}
+
+}  // extern "C"
+
+namespace fg {
+fg_status build_graph_impl(const fg_data* data, uint64_t seed, const fg_params* params, fg_graph* out,
+                           void* ws_dev, size_t ws_bytes, void* stream, fg_counters* counters,
+                           fg_timings* timings, const fg_visit_log* log) {
   Shape s;
   if (!make_shape(data, &s)) return FG_EINVAL;
   if (!check_params(params, s.n)) return FG_EINVAL;
@@ -908,7 +983,7 @@ fg_status fg_build_graph(const fg_data* data, uint64_t seed, const fg_params* pa
   for (uint32_t b = 0; b < Be; b++) {
     FG_TRY(mark());
     FG_TRY(harvest_launch(s, off[cur], ids[cur], roots, params, b, rows, cnt, ws_dev, m, st, nullptr,
-                          sched + sched_base, rank));
+                          sched + sched_base, rank, log));
     sched_base += n > (int64_t)b ? (n - (int64_t)b + Be - 1) / Be : 0;
     FG_TRY(mark());
     if (timings) {
@@ -970,6 +1045,84 @@ fg_status fg_build_graph(const fg_data* data, uint64_t seed, const fg_params* pa
   return status_error(c.status);
 }
 
+// Times block 0's harvest (over the substrate off/ids; a batched launch when
+// bi is set) for every candidate of the knobs that never change the graph:
+// the lanes per row (the library's shape, and the other one where the plain
+// harvest has it), the visited-table size (where ef_h and the row allow)
+// and the resident searches per compute unit (as many as fit, three
+// quarters, half), best of two launches each; leaves the fastest in *P and
+// its time in *best_ms.  The block's rows are overwritten.
+fg_status tune_harvest(const Shape& s, const uint64_t* off, const uint32_t* ids, const uint32_t* roots,
+                       fg_params* P, uint32_t* rows, uint32_t* cnt, void* ws, const WsMap& m, hipStream_t st,
+                       const BatchInfo* bi, const uint32_t* order, const uint32_t* rank, float* best_ms) {
+  const int ef = bi ? bi->ef_max : (int)P->ef_h;
+  std::vector<unsigned> lanes_c = {0u};
+  if (P->screen == FG_SCREEN_NONE)
+    for (unsigned ln : {4u, 8u}) {
+      int L = 0, nc = 0;
+      if (lanes_variant(s.dk, s.Q, (int)ln, &L, &nc)) lanes_c.push_back(ln);
+    }
+  hipEvent_t e0, e1;
+  FG_HIP(hipEventCreate(&e0));
+  FG_HIP(hipEventCreate(&e1));
+  float best = 3.0e38f;
+  unsigned best_tb = 0, best_wv = 0, best_ln = 0;
+  fg_params Q = *P;
+  for (unsigned ln : lanes_c) {
+    Q.lanes_per_row = ln;
+    const int nch = beam_chunks_per_lane(s, (int)ln);
+    std::vector<unsigned> tables;
+    if (ef <= 128 && ln == 0 && Q.screen == FG_SCREEN_NONE) tables = {512, 1024, 2048, 4096};
+    else if (ef <= 128) tables = {2048, 4096};
+    else tables = {4096};
+    for (unsigned tb : tables) {
+      Q.beam_table_slots = tb;
+      Q.waves_per_cu = 0;
+      const int hs = beam_table_slots(ef, false, table_request(&Q, nch), nch);
+      const int lk = Q.screen == FG_SCREEN_NONE ? (int)ln : 0;
+      int full = beam_grid(s, ef, false, hs, search_screen(Q.screen), 0, lk) / num_cus_host();
+      if (full < 1) full = 1;
+      for (unsigned wv : {0u, (unsigned)(full * 3 / 4), (unsigned)(full / 2)}) {
+        if (wv != 0 && (wv < 1 || (int)wv >= full)) continue;
+        Q.waves_per_cu = wv;
+        float t_best = 3.0e38f;
+        for (int rep = 0; rep < 2; rep++) {
+          fg_status rr = FG_OK;
+          if (hipEventRecord(e0, st) != hipSuccess) rr = FG_EHIP;
+          if (!rr) rr = harvest_launch(s, off, ids, roots, &Q, 0, rows, cnt, ws, m, st, bi, order, rank);
+          if (!rr && hipEventRecord(e1, st) != hipSuccess) rr = FG_EHIP;
+          if (!rr && hipEventSynchronize(e1) != hipSuccess) rr = FG_EHIP;
+          float ms = 0.f;
+          if (!rr && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rr = FG_EHIP;
+          if (rr) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return rr;
+          }
+          t_best = ms < t_best ? ms : t_best;
+        }
+        if (t_best < best) {
+          best = t_best;
+          best_tb = tb;
+          best_wv = wv;
+          best_ln = ln;
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  P->beam_table_slots = best_tb;
+  P->waves_per_cu = best_wv;
+  P->lanes_per_row = best_ln;
+  *best_ms = best;
+  return FG_OK;
+}
+
+}  // namespace fg
+
+extern "C" {
+
 // ---------------------------------------------------------------- autotune
 fg_status fg_autotune(const fg_data* data, const fg_params* params, const char* cache_path, void* ws_dev,
                       size_t ws_bytes, void* stream, fg_params* tuned) {
@@ -989,13 +1142,14 @@ fg_status fg_autotune(const fg_data* data, const fg_params* params, const char* 
       char line[256];
       bool hit = false;
       while (fgets(line, sizeof(line), f)) {
-        unsigned tb = 0, wv = 0;
+        unsigned tb = 0, wv = 0, ln = 0;
         const char* bar = strchr(line, '|');
         if (!bar || (size_t)(bar - line) != strlen(key) || strncmp(line, key, strlen(key))) continue;
-        if (sscanf(bar + 1, " table=%u waves=%u", &tb, &wv) == 2 && (tb == 1024 || tb == 2048 || tb == 4096) &&
-            wv <= 64) {
+        if (sscanf(bar + 1, " table=%u waves=%u lanes=%u", &tb, &wv, &ln) == 3 &&
+            (tb == 1024 || tb == 2048 || tb == 4096) && wv <= 64 && (ln == 0 || ln == 4 || ln == 8 || ln == 16)) {
           tuned->beam_table_slots = tb;
           tuned->waves_per_cu = wv;
+          tuned->lanes_per_row = ln;
           hit = true;
         }
       }
@@ -1033,49 +1187,13 @@ fg_status fg_autotune(const fg_data* data, const fg_params* params, const char* 
   r = screen_launch(ss, &P, ws_dev, m, st);
   if (r) return r;
   FG_HIP(fill_u32(reinterpret_cast<uint32_t*>(at(ws_dev, m.bits)), 0, (int64_t)kMaxWaveSlots * m.spill_words, st));
-  std::vector<unsigned> tables;
-  if (P.ef_h <= 64 && beam_chunks_per_lane(ss) == 1) tables = {1024, 2048, 4096};
-  else if (P.ef_h <= 128) tables = {2048, 4096};
-  else tables = {4096};
-  hipEvent_t e0, e1;
-  FG_HIP(hipEventCreate(&e0));
-  FG_HIP(hipEventCreate(&e1));
-  float best = 3.0e38f;
-  unsigned best_tb = tables[0], best_wv = 0;
-  for (unsigned tb : tables) {
-    P.beam_table_slots = tb;
-    P.waves_per_cu = 0;
-    const int hs = beam_table_slots((int)P.ef_h, false, table_request(&P), beam_chunks_per_lane(ss));
-    int full = beam_grid(ss, (int)P.ef_h, false, hs, (int)P.screen) / num_cus_host();
-    if (full < 1) full = 1;
-    for (unsigned wv : {0u, (unsigned)(full * 3 / 4), (unsigned)(full / 2)}) {
-      if (wv == 0 ? false : (wv < 1 || (int)wv >= full)) continue;
-      P.waves_per_cu = wv;
-      float t_best = 3.0e38f;
-      for (int rep = 0; rep < 2; rep++) {
-        fg_status rr = FG_OK;
-        if (hipEventRecord(e0, st) != hipSuccess) rr = FG_EHIP;
-        if (!rr) rr = harvest_launch(ss, off0, ids0, roots, &P, 0, rows, cnt, ws_dev, m, st);
-        if (!rr && hipEventRecord(e1, st) != hipSuccess) rr = FG_EHIP;
-        if (!rr && hipEventSynchronize(e1) != hipSuccess) rr = FG_EHIP;
-        float ms = 0.f;
-        if (!rr && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rr = FG_EHIP;
-        if (rr) {
-          (void)hipEventDestroy(e0);
-          (void)hipEventDestroy(e1);
-          return rr;
-        }
-        t_best = ms < t_best ? ms : t_best;
-      }
-      if (t_best < best) {
-        best = t_best;
-        best_tb = tb;
-        best_wv = wv;
-      }
-    }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  float best = 0.0f;
+  unsigned best_tb = 0, best_wv = 0, best_ln = 0;
+  r = tune_harvest(ss, off0, ids0, roots, &P, rows, cnt, ws_dev, m, st, nullptr, nullptr, nullptr, &best);
+  if (r) return r;
+  best_tb = P.beam_table_slots;
+  best_wv = P.waves_per_cu;
+  best_ln = P.lanes_per_row;
   Ctl c;
   r = read_ctl(ws_dev, m, st, &c);
   if (r) return r;
@@ -1083,10 +1201,11 @@ fg_status fg_autotune(const fg_data* data, const fg_params* params, const char* 
   if (r) return r;
   tuned->beam_table_slots = best_tb;
   tuned->waves_per_cu = best_wv;
+  tuned->lanes_per_row = best_ln;
   if (cache_path) {
     if (FILE* f = fopen(cache_path, "a")) {
-      fprintf(f, "%s| table=%u waves=%u  (block-0 harvest of %lld points: %.3f ms)\n", key, best_tb, best_wv,
-              (long long)ss.n, best);
+      fprintf(f, "%s| table=%u waves=%u lanes=%u  (block-0 harvest of %lld points: %.3f ms)\n", key, best_tb,
+              best_wv, best_ln, (long long)ss.n, best);
       fclose(f);
     }
   }
@@ -1181,7 +1300,8 @@ size_t fg_batched_workspace_size(const fg_data* const* data, const fg_params* co
 
 fg_status fg_build_graph_batched(const fg_data* const* data, const fg_params* const* params,
                                  const uint64_t* seeds, uint32_t count, fg_graph* const* outs, void* ws_dev,
-                                 size_t ws_bytes, void* stream, int use_hipgraph, fg_counters* counters) {
+                                 size_t ws_bytes, void* stream, int flags, fg_counters* counters) {
+  const bool use_hipgraph = (flags & FG_BATCH_HIPGRAPH) != 0;
   BatchPlan bp;
   if (!plan_batch(data, params, count, &bp)) return FG_EINVAL;
   if (!seeds || !outs) return set_error("seeds and outs are required"), FG_EINVAL;
@@ -1301,6 +1421,31 @@ fg_status fg_build_graph_batched(const fg_data* const* data, const fg_params* co
     }
     return FG_OK;
   };
+  // FG_BATCH_AUTOTUNE: the knobs that never change a graph (lanes per row,
+  // visited-table size, resident searches per compute unit) timed on this
+  // batch's own launch, block 0 of every instance over S_0; the choice is
+  // kept per batch shape for later calls.
+  if (flags & FG_BATCH_AUTOTUNE) {
+    char key[256];
+    snprintf(key, sizeof key, "batch count=%u N=%lld dk=%d Q=%d ef=%d T=%u R=%u B=%u", count, (long long)N, bp.s.dk,
+             bp.s.Q, bp.ef_max, T, R, Be);
+    uint32_t knobs[3];
+    if (tuned_lookup(key, knobs)) {
+      bp.P.beam_table_slots = knobs[0];
+      bp.P.waves_per_cu = knobs[1];
+      bp.P.lanes_per_row = knobs[2];
+    } else {
+      r = init_rows(st);
+      if (r) return r;
+      float ms = 0.0f;
+      r = tune_harvest(bp.s, off[0], ids[0], inst_roots, &bp.P, rows, cnt, ws_dev, m, st, &bi, sched, rank, &ms);
+      if (r) return r;
+      const uint32_t got[3] = {bp.P.beam_table_slots, bp.P.waves_per_cu, bp.P.lanes_per_row};
+      tuned_store(key, got);
+      r = reset_ctl(ws_dev, m, st);  // the timing launches' counters are not the build's
+      if (r) return r;
+    }
+  }
   r = init_rows(st);
   if (r) return r;
   if (use_hipgraph) {

@@ -104,10 +104,15 @@ struct BeamArgs {
   // the graph does not depend on the order (Prop. 1), locality does
   const uint32_t* order;
   // visited bitsets indexed by position in the processing order instead of
-  // by id (NULL: by id): a search's visits then cluster in few lines.  Used
-  // by rows of 2..4 chunks per lane, where it measured faster; the extra
-  // dependent load costs more than it saves for one-chunk and 16-chunk rows.
+  // by id (NULL: by id): a search's visits then cluster in fewer lines.
+  // Used by rows of 2..4 chunks per lane, where it measured faster; the
+  // extra dependent load costs more than it saves for one-chunk and
+  // 16-chunk rows.
   const uint32_t* rank;
+  // with rank: the CSR's ids paired with their ranks (idr[e] = (ids[e],
+  // rank[ids[e]])), so a scanned id's bit needs no lookup in rank, whose
+  // random reads compete with the rows for the L2 (NULL: look it up)
+  const uint2* idr;
   unsigned long long* queue;
   // with order: eight counters, one slice of the order per XCD (workgroup i
   // runs on XCD i mod 8), so each L2 sees neighbouring points; a wave whose
@@ -147,7 +152,20 @@ struct BeamArgs {
   // |x_i|^2 of every row (any float32 summation order): the Gram prune's
   // diagonal (NULL: no Gram prune)
   const float* norm;
+  // visit log (the logging instantiation only): points p with
+  // log_slot[p] >= 0 record the ids their search visits, in visit order,
+  // into log_ids[slot * log_cap ..] (the first log_cap of them), the total
+  // into log_len[slot], and the visit count after the roots and after each
+  // of the first kLogMarks - 1 expansions into log_marks[slot * kLogMarks ..]
+  const int* log_slot;
+  uint32_t* log_ids;
+  uint32_t* log_len;
+  uint32_t* log_marks;
+  int64_t log_cap;
+  int log_nslots;  // slots outside [0, log_nslots) are not logged
 };
+
+constexpr int kLogMarks = 17;
 
 constexpr int kGramMax = 1024;   // candidates the Gram-tile prune takes
 constexpr int kGramPF16 = 4;     // split-tile steps in flight
@@ -351,12 +369,46 @@ __device__ __forceinline__ void wave_sort_lds(T* a, int M) {
   }
 }
 
+// The same sort in device memory (the expanded sets longer than the
+// on-chip bound): each pass's stores are made visible, and the vector L1's
+// stale lines dropped, before the next pass reads them.
+__device__ __forceinline__ void wave_sort_global(uint64_t* a, int M) {
+  const int lane = lane_id();
+  for (int kb = 2; kb <= M; kb <<= 1) {
+    for (int jb = kb >> 1; jb > 0; jb >>= 1) {
+      for (int i = lane; i < M; i += 64) {
+        int ixj = i ^ jb;
+        if (ixj > i) {
+          uint64_t a0 = a[i], a1 = a[ixj];
+          bool up = (i & kb) == 0;
+          if ((a0 > a1) == up) {
+            a[i] = a1;
+            a[ixj] = a0;
+          }
+        }
+      }
+      __threadfence();
+      wave_sync();
+    }
+  }
+}
+
+// A word of the prune's live-candidate bits: in LDS, or (GA) in device
+// memory, where other lanes clear bits with atomics at L2, so the word is
+// read past the vector L1.
+template <bool GA>
+__device__ __forceinline__ uint32_t alive_word(const uint32_t* alive, int w) {
+  if constexpr (GA) return __hip_atomic_load(alive + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else return alive[w];
+}
+
 // Greedy occlusion prune of the mc candidates sk[0..mc) (sorted by key; the
 // key's high word is d(p, c)).  alive holds >= mc bits of LDS scratch, cid /
 // ckey 64 entries each.  Writes the kept ids to out[0..kept) (lane 0) and
 // returns kept; *pe counts the pair distances evaluated (each later live
 // candidate against each kept one until it dies).
-template <int DK, int L, int NCH>
+// GA: alive is in device memory (candidate sets beyond the on-chip bound).
+template <int DK, int L, int NCH, bool GA = false>
 __device__ int prune_wave(const RowSet& X, float alpha, int R, const uint64_t* sk, int mc,
                           uint32_t* alive, uint32_t* cid, uint64_t* ckey, uint32_t* out,
                           unsigned long long* pe) {
@@ -364,15 +416,18 @@ __device__ int prune_wave(const RowSet& X, float alpha, int R, const uint64_t* s
   const int g = lane % L;
   for (int w = lane; w < (mc + 31) / 32; w += 64) {
     int valid = mc - w * 32;
-    alive[w] = valid >= 32 ? 0xFFFFFFFFu : ((1u << valid) - 1u);
+    const uint32_t v = valid >= 32 ? 0xFFFFFFFFu : ((1u << valid) - 1u);
+    if constexpr (GA) __hip_atomic_store(alive + w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else alive[w] = v;
   }
+  if constexpr (GA) __threadfence();
   wave_sync();
   int kept = 0, i = 0;
   while (kept < R) {
     int nxt = -1;
     for (int base = i & ~63; base < mc; base += 64) {
       int j = base + lane;
-      bool live = j >= i && j < mc && ((alive[j >> 5] >> (j & 31)) & 1u);
+      bool live = j >= i && j < mc && ((alive_word<GA>(alive, j >> 5) >> (j & 31)) & 1u);
       uint64_t m = ballot(live);
       if (m) {
         nxt = base + __ffsll((long long)m) - 1;
@@ -391,7 +446,7 @@ __device__ int prune_wave(const RowSet& X, float alpha, int R, const uint64_t* s
     if constexpr (DK == U8L2) kn = group_sum_u32<L>(u8_selfdot<L, NCH>(kc));
     for (int base = i + 1; base < mc; base += 64) {
       int j = base + lane;
-      bool live = j < mc && ((alive[j >> 5] >> (j & 31)) & 1u);
+      bool live = j < mc && ((alive_word<GA>(alive, j >> 5) >> (j & 31)) & 1u);
       uint64_t m = ballot(live);
       int nl = popc64(m);
       if (nl == 0) continue;
@@ -406,6 +461,7 @@ __device__ int prune_wave(const RowSet& X, float alpha, int R, const uint64_t* s
         float scaled = alpha * dkc;
         if (scaled <= dpc) atomicAnd(&alive[j >> 5], ~(1u << (j & 31)));
       }
+      if constexpr (GA) __threadfence();  // the cleared bits, before the next read
       wave_sync();
     }
     i++;
@@ -414,12 +470,13 @@ __device__ int prune_wave(const RowSet& X, float alpha, int R, const uint64_t* s
 }
 
 // Waves per SIMD the register budget aims at: more searches in flight hide
-// more gather latency.  Four for one-chunk rows with the 1024-slot table
-// (9 KB of LDS per wave), three for rows of one or two chunks per lane,
-// two for the longest rows, else whatever the registers allow.
+// more gather latency.  Four for rows of one or two chunks per lane with a
+// table of at most 1024 slots (at most about 10 KB of LDS per wave), three
+// for such rows with larger tables, two for the longest rows, else whatever
+// the registers allow.
 template <int NCH, int HS>
 constexpr int beam_waves_per_eu() {
-  return (NCH == 1 && HS == 1024) ? 4 : (NCH <= 2 ? 3 : (NCH >= 16 ? 2 : 1));
+  return (NCH <= 2 && HS <= 1024) ? 4 : (NCH <= 2 ? 3 : (NCH >= 16 ? 2 : 1));
 }
 
 // ------------------------------------------------------------ Gram-tile prune
@@ -601,9 +658,18 @@ __device__ __forceinline__ void gram_row_block_split(const GramSplit& gs, const 
 // From the bfloat16 split the entries are sums of 3d exact products whose
 // magnitudes add up to at most (1 + 2^-8)^2 (1 + 2^-7 (1 + 2^-8)) |a||c| <=
 // 1.016 |a||c|, and the terms left out (<al,cl> and the residuals) are at
-// most 3.01 * 2^-16 |a||c|: gg = 3.1 * 2^-16 + 1.016 gamma(3d + 4), plus an
-// absolute 2^-100 (d + 4) for operands the matrix cores may flush to zero.
-// The result is doubled.
+// most 3.01 * 2^-16 |a||c|: gg = 3.1 * 2^-16 + 1.016 gamma(3d + 4).
+// Underflow is outside the standard model: the matrix cores may flush
+// operands and partial sums below 2^-126 to zero, and gradual underflow
+// errs absolutely.  An operand flushed to zero drops a product of at most
+// 2^-126 |c_k| (a sum over the row of at most 2^-126 sqrt(d) |c|, k of them
+// per element with k = 3 for the split), and each of the nk flushed or
+// underflowed partial results at most 2^-126; with |a| <= sqrt(|G_aa| +
+// 2^-120) (the norm's own float32 sum underflows by at most d 2^-149), the
+// three entries of d~ add 2^-124 (k sqrt(d) (|a| + |c|) + 2 nk), the one
+// entry of 1 - G_ac 2^-125 (k sqrt(d) (|a| + |c|) + nk); negligible for
+// rows of normal magnitude, it sends tests on tiny rows to the exact
+// recomputation.  The result is doubled.
 template <int DK>
 __device__ __forceinline__ float gram_eps(float dt, float gaa, float gcc, int d, bool split) {
   const float u = 5.9604645e-08f;  // 2^-24
@@ -620,7 +686,13 @@ __device__ __forceinline__ float gram_eps(float dt, float gaa, float gcc, int d,
     const float nn = __builtin_sqrtf(fabsf(gaa) * fabsf(gcc)) / (1.0f - gg);
     eps = (gg + gc) * nn + 4.0f * u * (1.0f + nn);
   }
-  if (split) eps += (float)(d + 4) * 7.888609e-31f;  // 2^-100 (d + 4)
+  const float na = __builtin_sqrtf(fabsf(gaa) + 7.5231638e-37f);  // 2^-120
+  const float nc = __builtin_sqrtf(fabsf(gcc) + 7.5231638e-37f);
+  const float flushed = (split ? 3.0f : 1.0f) * __builtin_sqrtf((float)d) * (na + nc);
+  if constexpr (DK == F32L2)
+    eps += 4.7019774e-38f * (flushed + 2.0f * (float)nk);  // 2^-124
+  else
+    eps += 2.3509887e-38f * (flushed + (float)nk);  // 2^-125
   return 2.0f * eps;
 }
 
@@ -761,7 +833,7 @@ __device__ int prune_gram(const RowSet& X, int d, const GramSplit& split, const 
   return kept;
 }
 
-template <int DK, int L, int NCH, int EFMAX, int HSLOTS, bool SEARCH, int SCR = SCR_NONE>
+template <int DK, int L, int NCH, int EFMAX, int HSLOTS, bool SEARCH, int SCR = SCR_NONE, bool LOG = false>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(beam_waves_per_eu<NCH, HSLOTS>())))
 k_beam(BeamArgs A) {
   __shared__ WaveLDS<EFMAX, HSLOTS> S;
@@ -770,11 +842,12 @@ k_beam(BeamArgs A) {
   const int64_t wslot = blockIdx.x;
   uint32_t* bits = A.spill_bits + wslot * A.spill_words;
   uint32_t* slist = A.spill_list + wslot * (int64_t)A.spill_cap;
-  uint64_t* E = A.Ebuf + wslot * (int64_t)A.Ecap;
+  // this slot's expanded list: Ecap keys, then Ecap bits of prune scratch
+  uint64_t* E = A.Ebuf + wslot * ((int64_t)A.Ecap + A.Ecap / 64);
   constexpr uint32_t HMASK = HSLOTS - 1;
   constexpr int HCAP = HSLOTS / 2 - 64;  // load <= 1/2; checked after every 64 insertions
   // rows in flight per lane group, sized to the register budget above
-  constexpr int kRB = (NCH >= 16) ? 1 : (NCH == 1 ? (HSLOTS == 1024 ? 8 : 12) : 16 / NCH);
+  constexpr int kRB = (NCH >= 16) ? 1 : (NCH == 1 ? (HSLOTS <= 1024 ? 8 : 12) : 16 / NCH);
   constexpr bool kRankBits = !SEARCH && NCH >= 2 && NCH <= 4;  // see BeamArgs::rank
   RowSet X{A.x, A.stride, A.Q};
 
@@ -842,19 +915,34 @@ k_beam(BeamArgs A) {
     int bsize = 0, cur = 0, hcount = 0, En = 0;
     bool spill = false, overflow = false;
     unsigned long long evals = 0;
+    int lslot = -1;  // this point's visit-log slot
+    if constexpr (LOG && !SEARCH) {
+      lslot = A.log_slot[p];
+      if (lslot >= A.log_nslots) lslot = -1;
+    }
 
     // Visit then evaluate a list of candidate ids (roots or a CSR row), 256
     // ids per step: the id loads, the visited checks (and the device bitset
     // atomics once the LDS table is full) of all 256 are issued before any
     // result is waited for; the new ids' rows are gathered 64*RB/L at a time;
     // keys that can still enter the beam are merged 64 at a time.
-    auto process = [&](const uint32_t* list, int64_t len) {
+    auto process = [&](const uint32_t* list, const uint2* plist, int64_t len) {
       for (int64_t base = 0; base < len; base += 256) {
-        uint32_t u[4];
+        uint32_t u[4], rk[4];
 #pragma unroll
         for (int k = 0; k < 4; k++) {
           int64_t j = base + k * 64 + lane;
-          u[k] = j < len ? list[j] : FG_NONE;
+          u[k] = FG_NONE;
+          rk[k] = FG_NONE;
+          if (j < len) {
+            if (kRankBits && plist) {
+              const uint2 pr = plist[j];
+              u[k] = pr.x;
+              rk[k] = pr.y;
+            } else {
+              u[k] = list[j];
+            }
+          }
         }
         bool isnew[4], need[4];
 #pragma unroll
@@ -900,7 +988,7 @@ k_beam(BeamArgs A) {
           uint32_t bi[4];
 #pragma unroll
           for (int k = 0; k < 4; k++) {
-            bi[k] = need[k] && A.rank ? A.rank[u[k]] : u[k];  // the bit of u
+            bi[k] = need[k] && A.rank ? (plist ? rk[k] : A.rank[u[k]]) : u[k];  // the bit of u
             if (need[k]) old[k] = atomicOr(&bits[bi[k] >> 5], 1u << (bi[k] & 31));
           }
 #pragma unroll
@@ -930,9 +1018,15 @@ k_beam(BeamArgs A) {
           if (isnew[k]) S.sid[nnew + popc64(m & lanes_below())] = u[k];
           nnew += popc64(m);
         }
+        const unsigned long long before = evals;
         evals += (unsigned long long)nnew;
         if (nnew == 0) continue;
         wave_sync();
+        if constexpr (LOG) {
+          if (lslot >= 0)
+            for (int i = lane; i < nnew; i += 64)
+              if ((int64_t)(before + i) < A.log_cap) A.log_ids[lslot * A.log_cap + (int64_t)(before + i)] = S.sid[i];
+        }
         if constexpr (SCR != SCR_NONE) {
           if (bsize == ef) {  // a full beam: its worst exact distance bounds entry
             const float w = ord_to_f32(key_hi(S.bkeys[cur][ef - 1]));
@@ -975,7 +1069,9 @@ k_beam(BeamArgs A) {
     };
 
     FG_TICK(6);
-    process(roots, A.T);
+    process(roots, nullptr, A.T);
+    if constexpr (LOG)
+      if (lslot >= 0 && lane == 0) A.log_marks[(int64_t)lslot * kLogMarks] = (uint32_t)evals;
     for (;;) {
       int first = -1;
       for (int base = 0; base < bsize; base += 64) {
@@ -997,9 +1093,16 @@ k_beam(BeamArgs A) {
       uint64_t s0 = A.off[v], s1 = A.off[v + 1];
       wave_sync();
       FG_TICK(5);
-      process(A.ids + s0, (int64_t)(s1 - s0));
+      process(A.ids + s0, kRankBits && A.idr ? A.idr + s0 : nullptr, (int64_t)(s1 - s0));
+      if constexpr (LOG)
+        if (lslot >= 0 && lane == 0 && En < kLogMarks) A.log_marks[(int64_t)lslot * kLogMarks + En] = (uint32_t)evals;
     }
     my_evals += evals;
+    if constexpr (LOG)
+      if (lslot >= 0 && lane == 0) {
+        A.log_len[lslot] = (uint32_t)evals;
+        for (int e = En + 1; e < kLogMarks; e++) A.log_marks[(int64_t)lslot * kLogMarks + e] = (uint32_t)evals;
+      }
 
     if constexpr (SEARCH) {
       for (int i = lane; i < A.k; i += 64) {
@@ -1018,10 +1121,13 @@ k_beam(BeamArgs A) {
       if (overflow) {
         if (lane == 0) atomicOr(A.status, 1);
       } else {
-        // Sort the expanded set (minus p) in LDS, then prune it.
-        uint64_t* sk = reinterpret_cast<uint64_t*>(S.htab);
+        // Sort the expanded set (minus p), then prune it: in LDS (the
+        // visited table's space) when it fits, else in place in this slot's
+        // device buffer.
+        const bool onchip = En <= HSLOTS / 2;
+        uint64_t* sk = onchip ? reinterpret_cast<uint64_t*>(S.htab) : E;
         int M = 64;
-        while (M < En) M <<= 1;
+        while (M < En) M <<= 1;  // <= Ecap: En < Ecap, a power of two
         wave_sync();
         for (int i = lane; i < M; i += 64) {
           uint64_t kk = FG_KEY_NONE;
@@ -1031,20 +1137,30 @@ k_beam(BeamArgs A) {
           }
           sk[i] = kk;
         }
-        wave_sync();
-        wave_sort_lds<uint64_t>(sk, M);
+        if (onchip) {
+          wave_sync();
+          wave_sort_lds<uint64_t>(sk, M);
+        } else {
+          __threadfence();
+          wave_sync();
+          wave_sort_global(sk, M);
+        }
         int mc = 0;
         for (int base = 0; base < M; base += 64) mc += popc64(ballot(sk[base + lane] != FG_KEY_NONE));
         FG_TICK(5);
         bool gram = false;
         if constexpr (DK != U8L2 && NCH >= 16)
-          gram = A.gram != nullptr && A.norm != nullptr && mc <= kGramMax && wslot < kGramSlots;
+          gram = onchip && A.gram != nullptr && A.norm != nullptr && mc <= kGramMax && wslot < kGramSlots;
         if (gram) {
           float* G = A.gram + (size_t)wslot * kGramMax * kGramMax;
           kept = prune_gram<DK, L, NCH>(X, A.d, A.split, A.norm, A.alpha, A.R, sk, mc, G, S.alive, S.cid, S.ckey,
                                         out, &my_pe, &my_rc);
-        } else
+        } else if (onchip) {
           kept = prune_wave<DK, L, NCH>(X, A.alpha, A.R, sk, mc, S.alive, S.cid, S.ckey, out, &my_pe);
+        } else {
+          uint32_t* galive = reinterpret_cast<uint32_t*>(E + A.Ecap);
+          kept = prune_wave<DK, L, NCH, true>(X, A.alpha, A.R, sk, mc, galive, S.cid, S.ckey, out, &my_pe);
+        }
         FG_TICK(4);
       }
       for (int t = kept + lane; t < A.R; t += 64) out[t] = FG_NONE;

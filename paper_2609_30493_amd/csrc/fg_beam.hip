@@ -11,8 +11,6 @@ namespace {
 
 template <int DK, int L, int NCH, int EFMAX, bool SEARCH>
 void* kernel_ptr(int hslots) {
-  if constexpr (!SEARCH && EFMAX <= 64 && NCH == 1)
-    if (hslots == 1024) return reinterpret_cast<void*>(&k_beam<DK, L, NCH, EFMAX, 1024, SEARCH>);
   if (hslots == 2048) return reinterpret_cast<void*>(&k_beam<DK, L, NCH, EFMAX, 2048, SEARCH>);
   return reinterpret_cast<void*>(&k_beam<DK, L, NCH, EFMAX, 4096, SEARCH>);
 }
@@ -65,7 +63,9 @@ int num_cus() {
 
 int num_cus_host() { return num_cus(); }
 
-int beam_chunks_per_lane(const Shape& s) {
+int beam_chunks_per_lane(const Shape& s, int lanes) {
+  int L = 0, nch = 0;
+  if (lanes && lanes_variant(s.dk, s.Q, lanes, &L, &nch)) return nch;
   if (s.Q <= 16) return 1;
   if (s.Q <= 32) return 2;
   if (s.Q <= 64) return 4;
@@ -73,23 +73,28 @@ int beam_chunks_per_lane(const Shape& s) {
 }
 
 // Slots of the on-chip visited table actually used for this launch: the
-// search kernels and ef > 128 always use 4096; 1024 exists for ef <= 64 and
-// rows of one 16-byte chunk per lane (else 2048); otherwise `hslots` (2048
-// or 4096) as requested.
+// search kernels and ef > 128 always use 4096; otherwise `hslots` (512,
+// 1024, 2048 or 4096) as requested.
 int beam_table_slots(int ef, bool search, int hslots, int nch) {
+  (void)nch;
   if (search || ef > 128) return 4096;
-  if (hslots == 1024) return ef <= 64 && nch == 1 ? 1024 : 2048;
-  return hslots == 2048 ? 2048 : 4096;
+  if (hslots == 512 || hslots == 1024 || hslots == 2048) return hslots;
+  return 4096;
 }
 
-static void* pick_kernel(const Shape& s, int ef, bool search, int hslots, int screen) {
+static void* pick_kernel(const Shape& s, int ef, bool search, int hslots, int screen, int lanes) {
+  if (screen == kBeamLog) return search ? nullptr : pick_log(s.dk, s.Q, ef);
+  if (lanes && !search && screen == SCR_NONE) {
+    if (void* k = pick_lanes(s.dk, s.Q, ef, hslots, lanes)) return k;
+  }
+  if (!search && screen == SCR_NONE && (hslots == 512 || hslots == 1024)) return pick_small(s.dk, s.Q, ef, hslots);
   if (screen == SCR_BF16) return search ? nullptr : pick_screen_bf16(s.dk, s.Q, ef, hslots);
   if (screen == SCR_FP8) return search ? nullptr : pick_screen_fp8(s.dk, s.Q, ef, hslots);
   return search ? pick<true>(s.dk, s.Q, ef, hslots) : pick<false>(s.dk, s.Q, ef, hslots);
 }
 
-int beam_grid(const Shape& s, int ef, bool search, int hslots, int screen, int waves_per_cu) {
-  void* k = pick_kernel(s, ef, search, hslots, screen);
+int beam_grid(const Shape& s, int ef, bool search, int hslots, int screen, int waves_per_cu, int lanes) {
+  void* k = pick_kernel(s, ef, search, hslots, screen, lanes);
   if (!k) return 0;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k), 64, 0) !=
@@ -102,8 +107,8 @@ int beam_grid(const Shape& s, int ef, bool search, int hslots, int screen, int w
 }
 
 hipError_t launch_beam(const Shape& s, BeamArgs& a, bool search, int grid, int hslots, hipStream_t st,
-                       int screen) {
-  void* k = pick_kernel(s, a.ef, search, hslots, screen);
+                       int screen, int lanes) {
+  void* k = pick_kernel(s, a.ef, search, hslots, screen, lanes);
   if (!k) return hipErrorInvalidValue;
   void* args[] = {&a};
   return hipLaunchKernel(reinterpret_cast<const void*>(k), dim3(grid), dim3(64), args, 0, st);

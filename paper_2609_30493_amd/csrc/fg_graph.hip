@@ -555,6 +555,23 @@ __global__ void k_rank_of(const uint32_t* order, int64_t len, uint32_t last, uin
 }
 }  // namespace
 
+namespace {
+// pairs[e] = (ids[e], rank[ids[e]]) for e < off[n] (read on the device).
+__global__ void k_csr_pairs(const uint64_t* off_n, const uint32_t* ids, const uint32_t* rank, uint2* pairs) {
+  const uint64_t nnz = *off_n;
+  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < nnz; e += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t u = ids[e];
+    pairs[e] = make_uint2(u, rank[u]);
+  }
+}
+}  // namespace
+
+hipError_t csr_rank_pairs(int64_t n, const uint64_t* off, const uint32_t* ids, const uint32_t* rank, uint2* pairs,
+                          hipStream_t st) {
+  k_csr_pairs<<<4096, 256, 0, st>>>(off + n, ids, rank, pairs);
+  return hipGetLastError();
+}
+
 hipError_t rank_of(const uint32_t* order, int64_t len, uint32_t last, uint32_t* rank, hipStream_t st) {
   k_rank_of<<<blocks_for(len + 1, 1024), 256, 0, st>>>(order, len, last, rank);
   return hipGetLastError();

@@ -13,7 +13,11 @@ namespace fg {
 
 // Bounds of the beam kernels' on-chip structures.
 constexpr int kHashSlotsMax = 4096;      // LDS visited table per wave (largest variant)
-constexpr int kEcap = kHashSlotsMax / 2; // expanded entries per search (buffer size)
+// Expanded entries per harvest search: up to half the visited table's
+// slots are sorted and pruned on chip, longer sets in the slot's device
+// buffer (kEcap keys, then kEcap bits of live flags); beyond kEcap the
+// search fails with a capacity error.
+constexpr int kEcap = 8192;
 constexpr int kSpillCap = 8192;          // ids remembered for clearing the spill bitset
 constexpr int kMaxWaveSlots = 4096;      // persistent grid bound (wave slots)
 constexpr int kMaxEfHarvest = 256;
@@ -34,12 +38,24 @@ bool make_shape(const fg_data* d, Shape* s);  // validates, sets error
 // beam_table_slots() the size the chosen kernel really uses.
 // screen (ScreenKind) selects the screened harvest kernels (fg_beam_sbf16.hip,
 // fg_beam_sfp8.hip: float32 rows of more than 16 chunks only).
+// lanes (0 = the default shape) asks for another lanes-per-row shape of the
+// plain harvest kernels (fg_beam_lanes.hip) where one exists.
 int beam_table_slots(int ef, bool search, int hslots, int nch);
-int beam_chunks_per_lane(const Shape& s);  // NCH of the kernel the dispatch picks
-int beam_grid(const Shape& s, int ef, bool search, int hslots, int screen = SCR_NONE, int waves_per_cu = 0);
+int beam_chunks_per_lane(const Shape& s, int lanes = 0);  // NCH of the kernel the dispatch picks
+int beam_grid(const Shape& s, int ef, bool search, int hslots, int screen = SCR_NONE, int waves_per_cu = 0,
+              int lanes = 0);
 hipError_t launch_beam(const Shape& s, BeamArgs& a, bool search, int grid, int hslots, hipStream_t st,
-                       int screen = SCR_NONE);
+                       int screen = SCR_NONE, int lanes = 0);
+// The lanes-per-row alternative for rows of Q chunks (false: none).
+bool lanes_variant(int dk, int Q, int lanes, int* L, int* nch);
+void* pick_lanes(int dk, int Q, int ef, int hslots, int lanes);
+// The plain harvest kernels with a 512- or 1024-slot table (fg_beam_small.hip).
+void* pick_small(int dk, int Q, int ef, int hslots);
 int num_cus_host();  // compute units of the current device
+// The harvest kernels with the visit log (fg_beam_log.hip): selected by
+// passing kBeamLog as `screen` to beam_grid / launch_beam (4096 slots).
+constexpr int kBeamLog = 16;
+void* pick_log(int dk, int Q, int ef);
 void* pick_screen_bf16(int dk, int Q, int ef, int hslots);
 void* pick_screen_fp8(int dk, int Q, int ef, int hslots);
 
@@ -72,6 +88,11 @@ hipError_t block_schedule(const uint32_t* order, int64_t len, int64_t n, uint32_
 // rank[order[i]] = i for i < len, rank[last] = len (order: every id but last;
 // last = 0xFFFFFFFF: no last).
 hipError_t rank_of(const uint32_t* order, int64_t len, uint32_t last, uint32_t* rank, hipStream_t st);
+// The substrate's ids with each id's rank beside it (pairs[e] = (ids[e],
+// rank[ids[e]]) for e < off[n], off[n] read on the device), for the
+// harvest's rank-indexed visited bitsets.
+hipError_t csr_rank_pairs(int64_t n, const uint64_t* off, const uint32_t* ids, const uint32_t* rank, uint2* pairs,
+                          hipStream_t st);
 // Exclusive scan of `count` uint32 values into uint64 offsets (count+1 entries).
 size_t scan_scratch_bytes(int64_t count);
 hipError_t exclusive_scan_u32_u64(const uint32_t* in, uint64_t* out, int64_t count,

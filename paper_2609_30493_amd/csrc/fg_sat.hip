@@ -1063,11 +1063,16 @@ hipError_t sat_build_multi(const Shape& s, uint32_t T, const std::vector<SatInst
     uint64_t* key_orig = a.key;
     a.key = src;  // sorted keys
     CK(launch((void*)&k_sat_perm_from_keys, nt, a, st));
-    // 2. acceptance rounds
+    // 2. acceptance rounds, four per check on the host: a round changes
+    // nothing on a bag whose candidates are all decided (resolve returns,
+    // filter finds no new neighbours), so the rounds after the last useful
+    // one are empty launches
     for (;;) {
-      CK(fill_u32(&ctl->active, 0, 1, st));
-      CK(launch(K.resolve, nseg, a, st));
-      CK(launch(K.filter, nt, a, st));
+      for (int r = 0; r < 4; r++) {
+        CK(fill_u32(&ctl->active, 0, 1, st));
+        CK(launch(K.resolve, nseg, a, st));
+        CK(launch(K.filter, nt, a, st));
+      }
       uint32_t active = 0;
       CK(hipMemcpyAsync(&active, &ctl->active, 4, hipMemcpyDeviceToHost, st));
       CK(hipStreamSynchronize(st));

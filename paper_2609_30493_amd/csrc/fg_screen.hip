@@ -7,30 +7,44 @@
 // row is scaled by the power of two 2^k that brings its largest magnitude
 // to at most 448, converted by the hardware, and read back as
 // code * 2^-k.  For every row the norm of the actual error |u^ - u| and the
-// norm |u| are accumulated in float64 and rounded up to float32, so the
-// margin the search uses bounds the copy that the search reads, whatever
-// rounding the conversion did.  For bfloat16 an optional split copy holds
-// hi and each element's remainder x - hi rounded to bfloat16 (lo), so that
-// hi + lo carries 16 significant bits, interleaved per 16-element step (32
-// bytes of hi, then 32 of lo): the prune tiles read both halves of a step
-// from one 64-byte span.
+// norm |u| are bounded from above in float32 (no float64 on the device): each
+// element error is exact in float32, the squares of the row's elements and
+// errors are summed after scaling by a power of two that keeps them below
+// one, and the sum is raised by its rounding bound (standard model, any
+// summation order: S <= (S~ + d 2^-125)(1 + gamma_d), the 2^-125 term
+// covering squares and sums flushed to zero), so the margin the search uses
+// bounds the copy that the search reads.  For bfloat16 an optional split
+// copy holds hi and each element's remainder x - hi rounded to bfloat16
+// (lo), so that hi + lo carries 16 significant bits, interleaved per
+// 16-element step (32 bytes of hi, then 32 of lo): the prune tiles read both
+// halves of a step from one 64-byte span.
 #include "fg_internal.h"
 
 namespace fg {
 
 namespace {
 
-// v >= 0: the float32 value next above or equal to v
-__device__ __forceinline__ float round_up_f32(double v) {
-  float f = (float)v;
-  if ((double)f < v) f = __uint_as_float(__float_as_uint(f) + 1u);
-  return f;
-}
-
-__device__ __forceinline__ double wave_sum_f64(double v) {
+__device__ __forceinline__ float wave_sum_f32(float v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
+}
+
+// An upper bound on sqrt(S) * 2^ex from the float32 sum s~ of the d squares
+// that make up S / 2^(2 ex) (each square below one):
+//   S / 2^(2 ex) <= (s~ + d 2^-125)(1 + gamma_d), gamma_d = d u / (1 - d u),
+// u = 2^-24; the factor is evaluated as 1 + 2 gamma_d, whose excess over
+// 1 + gamma_d (d u >= 4u here) covers the three roundings of the bound
+// itself.  The root (correctly rounded) is raised by 2^-22 of itself and
+// one unit in the last place.
+__device__ __forceinline__ float norm_bound(float s, int d, int ex) {
+  const float u = 5.9604645e-08f;
+  const float g = (float)d * u / (1.0f - (float)d * u);
+  const float S = (s + (float)d * 2.3509887e-38f) * (1.0f + 2.0f * g);  // 2^-125
+  float r = __builtin_sqrtf(S);
+  r = r * (1.0f + 2.3841858e-07f);                                         // 2^-22
+  r = __uint_as_float(__float_as_uint(r) + 1u);
+  return ldexpf(r, ex);
 }
 
 __device__ __forceinline__ float wave_max_f32(float v) {
@@ -56,27 +70,32 @@ __global__ void __launch_bounds__(256) k_make_screen(const uint8_t* x, int64_t s
   const int C = d / 4;
   for (int64_t i = wave; i < n; i += nwaves) {
     const float* row = reinterpret_cast<const float*>(x + i * stride);
+    float mx = 0.0f;
+    for (int c = lane; c < C; c += 64) {
+      const float4 v = *reinterpret_cast<const float4*>(row + 4 * c);
+      mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+    }
+    mx = wave_max_f32(mx);
+    // mx < 2^ex: every element and every element error scaled by 2^-ex is
+    // below one in magnitude (the errors are at most the elements' size)
+    int ex = 0;
+    if (mx > 0.0f) (void)frexpf(mx, &ex);
     float scale = 1.0f, inv = 1.0f;
     if constexpr (SCR == SCR_FP8) {
-      float mx = 0.0f;
-      for (int c = lane; c < C; c += 64) {
-        const float4 v = *reinterpret_cast<const float4*>(row + 4 * c);
-        mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
-      }
-      mx = wave_max_f32(mx);
       int k = 0;
       if (mx > 0.0f) {
-        // largest k with mx * 2^k <= 448
-        k = (int)floor(log2(448.0 / (double)mx));
-        while (ldexp((double)mx, k) > 448.0) k--;
-        while (ldexp((double)mx, k + 1) <= 448.0) k++;
+        // largest k with mx * 2^k <= 448 = 0.875 * 2^9, from mx = f 2^ex,
+        // f in [1/2, 1); the products with powers of two are exact
+        k = 9 - ex;
+        while (ldexpf(mx, k) > 448.0f) k--;
+        while (ldexpf(mx, k + 1) <= 448.0f) k++;
         if (k > 100) k = 100;
         if (k < -100) k = -100;
       }
       scale = ldexpf(1.0f, k);
       inv = ldexpf(1.0f, -k);
     }
-    double e2 = 0.0, n2 = 0.0;
+    float e2 = 0.0f, n2 = 0.0f;
     for (int c = lane; c < C; c += 64) {
       const float4 v = *reinterpret_cast<const float4*>(row + 4 * c);
       const float a[4] = {v.x, v.y, v.z, v.w};
@@ -116,9 +135,11 @@ __global__ void __launch_bounds__(256) k_make_screen(const uint8_t* x, int64_t s
       }
 #pragma unroll
       for (int t = 0; t < 4; t++) {
-        const double e = (double)back[t] - (double)a[t];
-        e2 += e * e;
-        n2 += (double)a[t] * (double)a[t];
+        // back and a are within a factor of two of each other (or back is
+        // zero), so their difference is exact in float32 (Sterbenz)
+        const float e = ldexpf(back[t] - a[t], -ex), y = ldexpf(a[t], -ex);
+        e2 = __builtin_fmaf(e, e, e2);
+        n2 = __builtin_fmaf(y, y, n2);
       }
     }
     if constexpr (SCR == SCR_BF16) {  // zero the padding (read by 16-element steps)
@@ -132,12 +153,11 @@ __global__ void __launch_bounds__(256) k_make_screen(const uint8_t* x, int64_t s
           *reinterpret_cast<uint2*>(at + 32) = make_uint2(0, 0);
         }
     }
-    e2 = wave_sum_f64(e2);
-    n2 = wave_sum_f64(n2);
-    if (lane == 0) {
-      // the float64 sums carry a relative error far below 2^-30
-      err[i] = round_up_f32(sqrt(e2) * (1.0 + 0x1p-30));
-      norm[i] = round_up_f32(sqrt(n2) * (1.0 + 0x1p-30));
+    e2 = wave_sum_f32(e2);
+    n2 = wave_sum_f32(n2);
+    if (lane == 0) {  // an all-zero row is copied exactly
+      err[i] = mx > 0.0f ? norm_bound(e2, d, ex) : 0.0f;
+      norm[i] = mx > 0.0f ? norm_bound(n2, d, ex) : 0.0f;
       sinv[i] = inv;
     }
   }

@@ -36,7 +36,7 @@ class fg_params(C.Structure):
     _fields_ = [("T", C.c_uint32), ("ef_h", C.c_uint32), ("R", C.c_uint32),
                 ("alpha", C.c_float), ("B", C.c_uint32), ("reprune_all", C.c_uint32),
                 ("beam_table_slots", C.c_uint32), ("screen", C.c_uint32),
-                ("waves_per_cu", C.c_uint32), ("reserved", C.c_uint32)]
+                ("waves_per_cu", C.c_uint32), ("lanes_per_row", C.c_uint32)]
 
 
 SCREEN_NONE, SCREEN_BF16, SCREEN_FP8E4M3, SCREEN_BF16_PRUNE = 0, 1, 2, 3
@@ -88,6 +88,7 @@ _SIGS = {
     "fg_merge_block": (C.c_int, [P, P, P, P, C.c_uint32, P, P, C.c_size_t, P]),
     "fg_finalize": (C.c_int, [P, P, P, P, P, P, C.c_size_t, P, P]),
     "fg_build_graph": (C.c_int, [P, C.c_uint64, P, P, P, C.c_size_t, P, P, P]),
+    "fg_build_graph_log": (C.c_int, [P, C.c_uint64, P, P, P, C.c_size_t, P, P, P, P]),
     "fg_search": (C.c_int, [P, P, P, C.c_int64, C.c_uint32, C.c_uint32, P, P, P, P,
                             C.c_size_t, P]),
     "fg_search_noalloc": (C.c_int, [P, P, P, C.c_int64, C.c_uint32, C.c_uint32, P, P, P, P]),
@@ -161,8 +162,8 @@ def make_data(x: torch.Tensor, metric: str = "l2") -> fg_data:
 
 
 def make_params(T, ef_h, R, alpha=1.2, B=1, reprune_all=0, beam_table_slots=0, screen=0,
-                waves_per_cu=0) -> fg_params:
-    return fg_params(T, ef_h, R, alpha, B, reprune_all, beam_table_slots, screen, waves_per_cu, 0)
+                waves_per_cu=0, lanes_per_row=0) -> fg_params:
+    return fg_params(T, ef_h, R, alpha, B, reprune_all, beam_table_slots, screen, waves_per_cu, lanes_per_row)
 
 
 def workspace_size(data: fg_data, params: fg_params) -> int:
@@ -256,6 +257,36 @@ def build_graph(data: fg_data, seed: int, params: fg_params, graph: fg_graph, ws
     return c.as_dict(), (t.as_dict() if timings else None)
 
 
+LOG_MARKS = 17
+
+
+class fg_visit_log(C.Structure):
+    _fields_ = [("slot_dev", C.c_void_p), ("nslots", C.c_uint32), ("cap", C.c_uint32),
+                ("ids_dev", C.c_void_p), ("len_dev", C.c_void_p), ("marks_dev", C.c_void_p)]
+
+
+def build_graph_log(data: fg_data, seed: int, params: fg_params, graph: fg_graph, ws,
+                    slot: torch.Tensor, cap: int, stream=None):
+    """fg_build_graph_log: the build plus the visit log of the points with
+    slot[p] >= 0 (int32, n entries).  Returns (counters, timings, ids
+    (nslots x cap, int32 bits of uint32), lens (nslots), marks (nslots x
+    LOG_MARKS))."""
+    nslots = int(slot.max().item()) + 1 if slot.numel() else 0
+    if nslots < 1:
+        _check(FG_EINVAL)
+    dev = slot.device
+    ids = torch.full((nslots, cap), -1, dtype=torch.int32, device=dev)
+    lens = torch.zeros(nslots, dtype=torch.int32, device=dev)
+    marks = torch.zeros((nslots, LOG_MARKS), dtype=torch.int32, device=dev)
+    log = fg_visit_log(slot.data_ptr(), nslots, cap, ids.data_ptr(), lens.data_ptr(), marks.data_ptr())
+    c = fg_counters()
+    t = fg_timings()
+    wp, wn = _ws(ws)
+    _check(lib().fg_build_graph_log(C.byref(data), seed, C.byref(params), C.byref(graph), wp, wn,
+                                    _stream(stream), C.byref(c), C.byref(t), C.byref(log)))
+    return c.as_dict(), t.as_dict(), ids, lens, marks
+
+
 def search(data: fg_data, graph: fg_graph, queries: torch.Tensor, k: int, L: int,
            out_ids, out_d, out_evals, ws, stream=None):
     wp, wn = _ws(ws)
@@ -294,7 +325,11 @@ def batched_workspace_size(datas, paramses) -> int:
     return int(lib().fg_batched_workspace_size(_ptr_array(datas), _ptr_array(paramses), len(datas)))
 
 
-def build_graph_batched(datas, paramses, seeds, graphs, ws=None, use_hipgraph=False, stream=None):
+BATCH_HIPGRAPH, BATCH_AUTOTUNE = 1, 2
+
+
+def build_graph_batched(datas, paramses, seeds, graphs, ws=None, use_hipgraph=False, stream=None,
+                        autotune=False):
     """Build len(datas) independent graphs together (fg_build_graph_batched);
     returns the summed counters and the workspace (reusable)."""
     count = len(datas)
@@ -307,7 +342,9 @@ def build_graph_batched(datas, paramses, seeds, graphs, ws=None, use_hipgraph=Fa
     sd = (C.c_uint64 * count)(*seeds)
     c = fg_counters()
     _check(lib().fg_build_graph_batched(_ptr_array(datas), _ptr_array(paramses), sd, count, _ptr_array(graphs),
-                                        wp, wn, _stream(stream), 1 if use_hipgraph else 0, C.byref(c)))
+                                        wp, wn, _stream(stream),
+                                        (BATCH_HIPGRAPH if use_hipgraph else 0) | (BATCH_AUTOTUNE if autotune else 0),
+                                        C.byref(c)))
     return c.as_dict(), ws
 
 

@@ -1,12 +1,17 @@
-"""The hot path at the full size and launch configuration that bench.py
-times (the SIFT-shaped uint8 build: n = 10^6, d = 128, T = 8, B = 8,
-ef_h = 64, R = 32, alpha = 1.2, a 1024-slot visited table, as many
-searches as fit), the GIST-shaped float32 build (d = 960, the matrix-core
-prune and scaffold tiles) and the GloVe-shaped cosine build (d = 100, the
-order-indexed visited bitsets) at n = 200,000, checked where the
-oracle cannot rebuild the whole graph in seconds: on sampled rows the oracle
-computes one by one (exact declared-order distances, its own prune, its
-roots) and through properties that hold at any size."""
+"""The hot path at full size, in the launch configuration bench.py times
+(library defaults for every tuning knob): the SIFT-shaped uint8 build
+(n = 10^6, d = 128, T = 8, B = 8, ef_h = 64, R = 32), the GloVe-shaped
+cosine build (n = 1,183,514, d = 100, T = 8, B = 8, ef_h = 128, R = 64) and
+the GIST-shaped float32 build (n = 10^6, d = 960, the matrix-core prune and
+scaffold tiles).  Each is compared with the oracle's own full-size build,
+recorded in tests/golden/fullsize.txt by an oracle-only script: the input
+digest first (the generators run on this host too), then the graph hash and
+every work counter.  Beside that, sampled rows the oracle computes one by
+one (exact declared-order distances, its own prune, its roots) and
+properties that hold at any size."""
+import hashlib
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -17,17 +22,35 @@ from paper_2609_30493_amd import datagen as gen
 pytestmark = pytest.mark.gpu
 
 SAMPLE = 300
-# workload, n, visited-table slots (0: the library's default)
-CASES = {"sift-1M": (gen.CFG2, 1_000_000, 1024), "gist-200k": (gen.CFG4, 200_000, 0),
-         "glove-200k": (gen.CFG3, 200_000, 0)}
+# workload, n, visited-table slots (0: the library's default, as bench.py),
+# key of the oracle's record
+CASES = {"sift-1M": (gen.CFG2, 1_000_000, 0, "cfg2"), "glove-1183514": (gen.CFG3, 1_183_514, 0, "cfg3"),
+         "gist-1M": (gen.CFG4, 1_000_000, 0, "cfg4")}
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize.txt")
+
+
+def _golden(key):
+    recs, cur = {}, None
+    if not os.path.exists(GOLDEN):
+        return None
+    for line in open(GOLDEN):
+        line = line.strip()
+        if line.startswith("[") and line.endswith("]"):
+            cur = recs.setdefault(line[1:-1], {})
+        elif cur is not None and "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            cur[k.strip()] = v.strip()
+    return recs.get(key)
 
 
 @pytest.fixture(scope="module", params=list(CASES))
 def full(request):
     from paper_2609_30493_amd import fgraft as F
-    W, n, table = CASES[request.param]
+    W, n, table, key = CASES[request.param]
     say(f"full-size build {request.param}: {W.name} at n = {n}")
     x = gen.workload_data(W, n)
+    digest = hashlib.sha256(np.ascontiguousarray(x).tobytes()).hexdigest()
+    say(f"  input sha256 {digest}")
     xd = torch.from_numpy(x).cuda()
     metric = "cosine" if W.metric == "cosine" else "l2"
     data = F.make_data(xd, metric)
@@ -36,12 +59,27 @@ def full(request):
     gn, gc, sp, rt = empty_u32(n, W.R), empty_u32(n, fill=0), empty_u32(n), empty_u32(W.T)
     G = F.make_graph(gn, gc, sp, rt, W.T)
     c, _ = F.build_graph(data, W.build_seed, params, G, ws, timings=True)
-    out = dict(W=W, n=n, metric=metric, x=x, data=data, params=params, ws=ws, G=G, counters=c,
+    out = dict(W=W, n=n, key=key, digest=digest, metric=metric, x=x, data=data, params=params, ws=ws, G=G,
+               counters=c,
                hash=F.graph_hash(G), nbrs=host_u32(gn), cnt=host_u32(gc), spine=host_u32(sp),
                roots=host_u32(rt))
     yield out
     del out, ws, G, gn, gc, sp, rt, xd
     torch.cuda.empty_cache()
+
+
+def test_fullsize_equals_the_oracle_build(full):
+    """Prop. 1 at full size: the graph hash and every counter equal the
+    oracle's build of the same input (recorded by an oracle-only script)."""
+    g = _golden(full["key"])
+    if g is None:
+        pytest.skip(f"no oracle record for {full['key']} in tests/golden/fullsize.txt")
+    assert full["digest"] == g["input_sha256"], \
+        "the generator produced different input bytes on this host than where the oracle ran"
+    assert f"{full['hash']:#018x}" == g["graph_hash"]
+    for k in ("scaffold_evals", "harvest_evals", "prune_evals", "finalize_evals", "expansions"):
+        assert full["counters"][k] == int(g[k]), k
+    say(f"  {full['key']}: hash {g['graph_hash']} and counters equal the oracle's")
 
 
 def _sample(n, seed):

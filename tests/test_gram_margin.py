@@ -25,8 +25,14 @@ def margin(dt, gaa, gcc, d, metric, split):
     else:
         nn = np.sqrt(abs(gaa) * abs(gcc)) / (1 - gg)
         eps = (gg + gc) * nn + 4 * U * (1 + nn)
-    if split:
-        eps += (d + 4) * 2.0 ** -100
+    # underflow: flushed operands (k products per element) and nk flushed or
+    # underflowed partial results, at most 2^-126 each
+    na, nc = np.sqrt(abs(gaa) + 2.0 ** -120), np.sqrt(abs(gcc) + 2.0 ** -120)
+    flushed = (3 if split else 1) * np.sqrt(d) * (na + nc)
+    if metric == "l2":
+        eps += 2.0 ** -124 * (flushed + 2 * nk)
+    else:
+        eps += 2.0 ** -125 * (flushed + nk)
     return eps
 
 
@@ -38,9 +44,24 @@ def bf16_split(x):
     return hi.numpy(), lo.numpy()
 
 
+TINY = np.float32(2.0 ** -126)
+
+
+def ftz(v):
+    """Flush float32 values below the normal range to zero."""
+    v = np.asarray(v, dtype=np.float32)
+    return np.where(np.abs(v) < TINY, np.float32(0), v).astype(np.float32)
+
+
 def fsum(terms, mode):
-    """Float32 sum of float32 terms in a given order."""
+    """Float32 sum of float32 terms in a given order ("ftz": sequential,
+    every partial sum flushed to zero below the normal range)."""
     terms = np.asarray(terms, dtype=np.float32)
+    if mode == "ftz":
+        acc = np.float32(0)
+        for t in terms:
+            acc = ftz(np.float32(acc + t))[()]
+        return acc
     if mode == "seq":
         return np.cumsum(terms, dtype=np.float32)[-1]
     if mode == "rev":
@@ -54,11 +75,12 @@ def fsum(terms, mode):
 
 
 def gram_entry(a, c, split, mode):
+    flush = ftz if mode == "ftz" else (lambda v: np.asarray(v, dtype=np.float32))
     if not split:
-        return fsum((a.astype(np.float64) * c.astype(np.float64)).astype(np.float32), mode)
-    ah, al = bf16_split(a)
-    ch, cl = bf16_split(c)
-    f = lambda u, v: (u.astype(np.float64) * v.astype(np.float64)).astype(np.float32)
+        return fsum(flush((flush(a).astype(np.float64) * flush(c).astype(np.float64)).astype(np.float32)), mode)
+    ah, al = (flush(v) for v in bf16_split(a))
+    ch, cl = (flush(v) for v in bf16_split(c))
+    f = lambda u, v: flush((u.astype(np.float64) * v.astype(np.float64)).astype(np.float32))  # noqa: E731
     if mode == "steps":  # the tile's order: per 16 elements al*ch, ah*cl, ah*ch
         terms = []
         for k in range(0, a.size, 16):
@@ -86,6 +108,13 @@ def pairs(metric, rng, d):
     out.append((o, (o + rng.standard_normal(d) * 1e-3).astype(np.float32)))
     m = (rng.standard_normal(d) * np.logspace(-20, 5, d)).astype(np.float32)
     out.append((m, (m * 1.001).astype(np.float32)))
+    # rows whose squares and products fall below the normal range
+    for e in (-64, -70, -75):
+        t = np.ldexp(rng.standard_normal(d), e).astype(np.float32)
+        out.append((t, (t + np.ldexp(rng.standard_normal(d), e - 2)).astype(np.float32)))
+    z = np.ldexp(rng.standard_normal(d), -70)
+    z[: d // 2] *= 2.0 ** 60
+    out.append((z.astype(np.float32), (z * 0.999).astype(np.float32)))
     if metric == "cosine":
         out = [(a / np.linalg.norm(a.astype(np.float64)), c / np.linalg.norm(c.astype(np.float64)))
                for a, c in out if np.linalg.norm(a) > 0 and np.linalg.norm(c) > 0]
@@ -99,7 +128,7 @@ def pairs(metric, rng, d):
 def test_gram_margin_bounds_exact_distance(fgo, metric, split, d):
     rng = np.random.default_rng(d + 2 * split + 5 * (metric == "cosine"))
     worst = 0.0
-    modes = ("seq", "rev", "pair", "steps") if split else ("seq", "rev", "pair")
+    modes = ("seq", "rev", "pair", "steps", "ftz") if split else ("seq", "rev", "pair", "ftz")
     for a, c in pairs(metric, rng, d):
         D = fgo.Data(np.stack([a, c]), metric=metric)
         exact = float(fgo.dist(D, 0, 1))

@@ -81,3 +81,46 @@ def test_coherent_blocks_brute_force():
         want = sorted(int(size[v]) for v in range(n)
                       if size[v] <= cap and (parent[v] == 0xFFFFFFFF or size[parent[v]] > cap))
         assert sorted(bench.coherent_blocks(parent, cap).tolist()) == want, trial
+
+
+def test_coherent_block_members_hand_tree(bench):
+    # 0 is the root; 1 and 2 its children; 3, 4 under 1; 5 under 2; 6 under 5
+    N = 0xFFFFFFFF
+    parent = np.array([N, 0, 0, 1, 1, 2, 5], np.uint32)
+    blocks = bench.coherent_block_members(parent, 3)
+    got = sorted(b.tolist() for b in blocks)
+    # subtree(1) = {1, 3, 4} and subtree(2) = {2, 5, 6}: each of size 3 under a root of size 7
+    assert got == [[1, 3, 4], [2, 5, 6]]
+    # sizes agree with coherent_blocks on random trees, and blocks are disjoint
+    rng = np.random.default_rng(4)
+    for trial in range(20):
+        n = int(rng.integers(2, 300))
+        par = np.full(n, N, np.uint32)
+        for v in range(1, n):
+            par[v] = rng.integers(0, v)
+        cap = int(rng.integers(1, 40))
+        mem = bench.coherent_block_members(par, cap)
+        assert sorted(len(b) for b in mem) == sorted(bench.coherent_blocks(par, cap).tolist())
+        allp = np.concatenate(mem) if mem else np.zeros(0, np.int64)
+        assert len(set(allp.tolist())) == len(allp)
+        for b in mem:  # preorder from the block's root: every point's parent precedes it
+            pos = {int(v): i for i, v in enumerate(b)}
+            for v in b[1:]:
+                assert int(par[v]) in pos and pos[int(par[v])] < pos[int(v)]
+
+
+def test_lockstep_stats_hand_example(bench):
+    import torch
+    t = lambda *v: torch.tensor(v, dtype=torch.long)  # noqa: E731
+    V = [t(1, 2, 3, 4), t(3, 4, 5, 6), t(4, 6, 7, 8)]
+    W = [t(2, 3), t(3, 5, 6), t(6, 8)]
+    st = bench.lockstep_stats(V, W, repeat=2)
+    # union {1..8}: density 12 / (3 * 8)
+    assert st["union"] == 8 and st["density"] == pytest.approx(12 / 24)
+    assert st["mean_V"] == pytest.approx(4.0)
+    # adjacent pairs: (W0, W1) share {3}, (W1, W2) share {6}; mean sizes 2.5 and 2.5
+    assert st["shared_exp_1_10"] == pytest.approx(2 / 5)
+    # targets seen by >= 2 points: 3 (x2), 4 (x3), 6 (x2): 7 of 12 evaluations
+    assert st["evals_to_targets_seen_by_2_or_more"] == pytest.approx(7 / 12)
+    # identical visited sets: density 1
+    assert bench.lockstep_stats([t(1, 2), t(1, 2)], [t(1), t(1)])["density"] == pytest.approx(1.0)
