@@ -616,7 +616,9 @@ def screen_compare(args):
             b = np.array([r["build_s"] for r in res[f]])
             ev = res[f][0]["evals"]
             rej = res[f][0]["rejected"]
-            narrow = {0: 0, 1: 2 * w.d, 2: w.d, 3: 0}[f]
+            # a screened evaluation reads the narrow row's codes and its
+            # 16-byte trailer (error norm, norm, fp8 factor)
+            narrow = {0: 0, 1: (2 * w.d + 31) // 32 * 32 + 16, 2: (w.d + 15) // 16 * 16 + 16, 3: 0}[f]
             e = {"harvest_ms_median": float(np.median(h)), "build_s_median": float(np.median(b)),
                  "harvest_evals_per_s": float(ev / (np.median(h) / 1e3)),
                  "screen_rejected_frac": rej / ev,
@@ -769,8 +771,12 @@ def main():
                          "d = 960 build")
     ap.add_argument("--extra", default="cfg2,cfg4",
                     help="other full-size workloads measured once each after the line (extra keys)")
-    ap.add_argument("--table", type=int, default=0, choices=(0, 1024, 2048, 4096),
+    ap.add_argument("--table", type=int, default=0, choices=(0, 512, 1024, 2048, 4096),
                     help="on-chip visited-table slots per search (0 = library default)")
+    ap.add_argument("--tune", action="store_true",
+                    help="pick the visited-table size, searches per compute unit and lanes per row "
+                         "with fg_autotune before the warm-up (off by default: the tuner times block 0 "
+                         "of a 50,000-row prefix, and the library's defaults come from full-size sweeps)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed steps, copy 1 GiB device to device (a plain copy "
                          "kernel of known size, to scale profiler byte counters)")
@@ -835,6 +841,13 @@ def run_builds(key, w, args, steps, warmup, xd=None, x=None):
     params = F.make_params(w.T, w.ef_h, w.R, w.alpha, w.B, beam_table_slots=args.table)
     ws = F.alloc_workspace(data, params)
     log(f"[bench] {key}: workspace {ws.numel() / 2**30:.2f} GiB")
+    tuned = None
+    if getattr(args, "tune", False):
+        t0 = time.perf_counter()
+        params = F.autotune(data, params, ws)
+        tuned = {"beam_table_slots": params.beam_table_slots, "waves_per_cu": params.waves_per_cu,
+                 "lanes_per_row": params.lanes_per_row, "tune_s": time.perf_counter() - t0}
+        log(f"[bench] {key}: tuned {tuned}")
 
     def u32(*shape):
         return torch.full(shape, -1, dtype=torch.int32, device="cuda")
@@ -861,7 +874,8 @@ def run_builds(key, w, args, steps, warmup, xd=None, x=None):
     ghash = F.graph_hash(G)
     rec = {"workload": w.name, "n": n, "d": w.d, "metric": metric, "T": w.T, "B": w.B, "ef_h": w.ef_h,
            "R": w.R, "alpha": w.alpha, "seed": w.build_seed,
-           "beam_table_slots": args.table or "library default",
+           "beam_table_slots": (tuned["beam_table_slots"] if tuned else args.table) or "library default",
+           "tuned": tuned,
            "harvest_evals_per_s": ev / (hms / 1e3), "build_s": wall / steps,
            "phase_ms": {k: t0_[k] for k in ("scaffold_ms", "harvest_ms", "merge_ms", "finalize_ms")},
            "harvest_evals_per_build": c0["harvest_evals"], "counters": c0, "graph_hash": f"{ghash:#018x}",

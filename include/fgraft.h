@@ -95,8 +95,9 @@ typedef struct {
  * symmetrised candidate set exceeds R; 1 re-prunes every row.
  * beam_table_slots is a tuning knob that never changes the graph: the size
  * of each harvest search's on-chip visited table, 512, 1024, 2048 or 4096
- * (0 = 4096 for FG_F32 rows of more than 256 elements, else 2048 when
- * ef_h <= 128 and 4096 otherwise; ef_h > 128 always uses 4096; 512 and
+ * (0 = 4096 for FG_F32 rows of more than 256 elements or ef_h > 128, else
+ * 1024 for rows of at most 16 bytes per lane -- uint8 d <= 256 or FG_F32
+ * d <= 64 -- and 2048 for the rest; ef_h > 128 always uses 4096; 512 and
  * 1024 apply to the unscreened harvest with ef_h <= 128 and the library's
  * lanes per row, else 2048 is used).  Smaller tables let more searches run
  * per compute unit; a search whose visits outgrow its table continues in a
@@ -357,8 +358,11 @@ fg_status fg_leaf_knn(const fg_data* data, uint32_t leaf_size, uint32_t R,
  * row i of the data as bfloat16 (round to nearest even) or as fp8 e4m3 (OCP)
  * codes of x * 2^k, k the largest integer with max|x_i| * 2^k <= 448, in
  * the data's element order, rows fg_screen_row_bytes(d, screen) bytes apart
- * (bfloat16: 2d rounded up to a multiple of 32, pad bytes written as zero;
- * fp8: d rounded up to a multiple of 16, pad bytes not written).
+ * (a whole number of 128-byte lines).  A row holds the codes (bfloat16: 2d
+ * bytes rounded up to a multiple of 32, pad bytes written as zero; fp8: d
+ * rounded up to a multiple of 16, pad bytes not written), then a 16-byte
+ * trailer of four floats (err, norm, sinv, 0) equal to the values below,
+ * then padding (zero for bfloat16, not written for fp8).
  * err_dev[i] >= |x^_i - x_i| and norm_dev[i] >= |x_i| (float32 sums of
  * scaled squares raised by their rounding bound), sinv_dev[i] = 2^-k (1 for
  * bfloat16), where x^_i is the copy read back (fp8: code * 2^-k).  FG_F32
@@ -369,7 +373,7 @@ fg_status fg_screen_copy(const fg_data* data, uint32_t screen, void* xs_dev,
                          void* stream);
 
 /* Autotuning of the harvest's knobs (none changes the graph): the
- * visited-table size (beam_table_slots 1024 / 2048 / 4096, where ef_h and
+ * visited-table size (beam_table_slots 512 / 1024 / 2048 / 4096, where ef_h and
  * the row size allow), the resident searches per compute unit
  * (waves_per_cu) and the lanes that share one row (lanes_per_row: the
  * library's shape and the other one where it exists).  On the first

@@ -97,18 +97,21 @@ int search_screen(uint32_t screen) {
 
 uint32_t b_eff(const fg_params* p) { return p->B > 1 ? p->B : 1; }
 
-// Visited-table size for the harvest: the caller's choice, else 2048 slots
-// when ef_h <= 128 (more searches resident per compute unit; measured faster
-// on the 1M uint8 build) and 4096 otherwise.  Rows of more than 64 chunks
-// (nch 16) take 4096: their registers already hold residency at two searches
-// per SIMD, and the larger table keeps searches off the device bitset
-// (measured 6% faster on the 200,000 x 960 build).
+// Visited-table size for the harvest: the caller's choice, else by row
+// shape, from full-size sweeps of every size.  Rows of one chunk per lane
+// with ef_h <= 128 take 1024 (four searches per SIMD; the 1M x 128 uint8
+// harvest: 528 ms, against 523 at 512 and 559 at 2048); other rows with
+// ef_h <= 128 take 2048 (the 1,183,514 x 100 cosine harvest: 3.65 s, against
+// 3.78 at 512 and 3.69 at 4096); rows of more than 64 chunks (nch 16) take
+// 4096: their registers already hold residency at two searches per SIMD and
+// the larger table keeps searches off the device bitset (the 10^6 x 960
+// harvest: 1.88 s, against 1.98 at 2048); ef_h > 128 takes 4096.
 int table_request(const fg_params* p, int nch = 1) {
   if (p->beam_table_slots == 512 || p->beam_table_slots == 1024 || p->beam_table_slots == 2048 ||
       p->beam_table_slots == 4096)
     return (int)p->beam_table_slots;
-  if (nch >= 16) return 4096;
-  return p->ef_h <= 128 ? 2048 : 4096;
+  if (nch >= 16 || p->ef_h > 128) return 4096;
+  return nch == 1 ? 1024 : 2048;
 }
 
 // ---------------------------------------------------------------- workspace
@@ -121,7 +124,7 @@ struct WsMap {
   size_t sgoff, sgids;                      // search graph
   size_t off[2], ids[2], rows, cnt, tparent, roots;  // the whole build
   size_t sat;
-  size_t xs, xs_err, xs_norm, xs_sinv;      // screened harvest (last: only they depend on d)
+  size_t xs;                                // screened harvest (last: only they depend on d)
   size_t xsp;                               // the bfloat16 split (interleaved hi/lo)
   int64_t xsp_stride;
   size_t sched;                             // every block's points in scaffold order
@@ -202,9 +205,6 @@ WsMap ws_map(int64_t n, const fg_params* p, int d = 0) {
       m.xsp_stride = split_stride(d);
       m.xsp = take(un * (uint64_t)m.xsp_stride);
     }
-    m.xs_err = take(un * 4);
-    m.xs_norm = take(un * 4);
-    m.xs_sinv = take(un * 4);
   }
   m.total = o;
   return m;
@@ -334,9 +334,7 @@ fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* id
   } else if (screen) {
     a.xs = reinterpret_cast<const uint8_t*>(at(ws, m.xs));
     a.xs_stride = m.xs_stride;
-    a.xs_err = reinterpret_cast<const float*>(at(ws, m.xs_err));
-    a.xs_norm = reinterpret_cast<const float*>(at(ws, m.xs_norm));
-    a.xs_sinv = reinterpret_cast<const float*>(at(ws, m.xs_sinv));
+    a.xs_tail = screen_tail(s.d, copy_kind(P->screen));
   }
   FG_HIP(launch_beam(s, a, false, grid, hslots, st, screen, lanes));
   return FG_OK;
@@ -347,10 +345,8 @@ fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* id
 fg_status screen_launch(const Shape& s, const fg_params* P, void* ws, const WsMap& m, hipStream_t st) {
   if (m.norm && s.dk != U8L2) FG_HIP(row_sq_norms(s, reinterpret_cast<float*>(at(ws, m.norm)), st));
   if (!P->screen) return FG_OK;
-  FG_HIP(make_screen(s, copy_kind(P->screen), m.xs ? reinterpret_cast<uint8_t*>(at(ws, m.xs)) : nullptr,
-                     reinterpret_cast<float*>(at(ws, m.xs_err)), reinterpret_cast<float*>(at(ws, m.xs_norm)),
-                     reinterpret_cast<float*>(at(ws, m.xs_sinv)), st,
-                     m.xsp ? reinterpret_cast<uint8_t*>(at(ws, m.xsp)) : nullptr));
+  FG_HIP(make_screen(s, copy_kind(P->screen), m.xs ? reinterpret_cast<uint8_t*>(at(ws, m.xs)) : nullptr, nullptr,
+                     nullptr, nullptr, st, m.xsp ? reinterpret_cast<uint8_t*>(at(ws, m.xsp)) : nullptr));
   return FG_OK;
 }
 

@@ -128,14 +128,12 @@ struct BeamArgs {
   unsigned long long* counters;  // evals, expansions, prune pairs, spilled, screen-rejected, prune rechecks
   int* status;                   // bit 0: expanded-list overflow
   // screened harvest: the narrow copy (row stride xs_stride bytes, the
-  // elements in data order), per row the norm of its quantisation error
-  // |u^ - u|, its norm |u| (both rounded up) and the fp8 dequantisation
-  // factor (a power of two)
+  // elements in data order), each row with a trailer at byte xs_tail:
+  // the norm of its quantisation error |u^ - u|, its norm |u| (both rounded
+  // up) and the fp8 dequantisation factor (a power of two)
   const uint8_t* xs;
   int64_t xs_stride;
-  const float* xs_err;
-  const float* xs_norm;
-  const float* xs_sinv;
+  int64_t xs_tail;
   int d;
   // batched builds: many instances in one id space.  inst_of[p] is p's
   // instance (0xFFFF: an unused id, skipped), whose T roots are
@@ -173,13 +171,35 @@ constexpr int kGramSlots = 2048; // wave slots that have Gram scratch
 
 enum ScreenKind { SCR_NONE = 0, SCR_BF16 = 1, SCR_FP8 = 2 };
 
-// Screened distance between the query's exact float32 chunks `a` and row
-// `srow` of the narrow copy (lane g reads the narrow form of its own chunks
-// q = g + L*i), reduced over the group.  Any summation order: the margin
-// below holds for all of them.
+// One narrow row's codes as lane g of a group holds them: chunk q = g + L*i
+// (four elements) as two words of bfloat16 or one word of fp8, zero past Q.
+template <int NCH, int SCR>
+struct NarrowChunks {
+  uint32_t w[NCH * (SCR == SCR_BF16 ? 2 : 1)];
+};
+
+template <int L, int NCH, int SCR>
+__device__ __forceinline__ void load_narrow(NarrowChunks<NCH, SCR>& r, const uint8_t* srow, int Q, int g) {
+#pragma unroll
+  for (int i = 0; i < NCH; i++) {
+    const int q = g + L * i;
+    if constexpr (SCR == SCR_BF16) {
+      uint2 v = make_uint2(0, 0);
+      if (q < Q) v = *reinterpret_cast<const uint2*>(srow + 8 * (size_t)q);
+      r.w[2 * i] = v.x;
+      r.w[2 * i + 1] = v.y;
+    } else {
+      r.w[i] = q < Q ? *reinterpret_cast<const uint32_t*>(srow + 4 * (size_t)q) : 0u;
+    }
+  }
+}
+
+// Screened distance between the query's exact float32 chunks `a` and a
+// narrow row's chunks, reduced over the group.  Any summation order: the
+// margin below holds for all of them.
 template <int DK, int L, int NCH, int SCR>
-__device__ __forceinline__ float group_screen(const Chunks<L, NCH>& a, const uint8_t* srow, float sinv, int Q,
-                                              int g) {
+__device__ __forceinline__ float group_screen(const Chunks<L, NCH>& a, const NarrowChunks<NCH, SCR>& r, float sinv,
+                                              int Q, int g) {
   float acc = 0.0f;
 #pragma unroll
   for (int i = 0; i < NCH; i++) {
@@ -188,11 +208,11 @@ __device__ __forceinline__ float group_screen(const Chunks<L, NCH>& a, const uin
       const float4 xa = *reinterpret_cast<const float4*>(&a.c[i]);
       float4 xb;
       if constexpr (SCR == SCR_BF16) {
-        const uint2 w = *reinterpret_cast<const uint2*>(srow + 8 * (size_t)q);
-        xb = make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xFFFF0000u), __uint_as_float(w.y << 16),
-                         __uint_as_float(w.y & 0xFFFF0000u));
+        const uint32_t w0 = r.w[2 * i], w1 = r.w[2 * i + 1];
+        xb = make_float4(__uint_as_float(w0 << 16), __uint_as_float(w0 & 0xFFFF0000u), __uint_as_float(w1 << 16),
+                         __uint_as_float(w1 & 0xFFFF0000u));
       } else {
-        const int w = *reinterpret_cast<const int*>(srow + 4 * (size_t)q);
+        const int w = (int)r.w[i];
         const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8(w, false);
         const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8(w, true);
         xb = make_float4(lo[0] * sinv, lo[1] * sinv, hi[0] * sinv, hi[1] * sinv);
@@ -227,11 +247,19 @@ __device__ __forceinline__ float group_screen(const Chunks<L, NCH>& a, const uin
 //     (gs + gc) |p| (|u| + E), and the two roundings of 1 - s add
 //     2^-23 (1 + |p| (|u| + E)).
 // The result is doubled, which also covers the rounding of eps itself.
-template <int DK>
-__device__ __forceinline__ float screen_eps(float dt, int d, float E, float np, float nu) {
+struct ScreenGammas {
+  float gs, gc;
+};
+
+__device__ __forceinline__ ScreenGammas screen_gammas(int d) {
   const float u = 5.9604645e-08f;  // 2^-24
-  const float gs = (d + 12) * u / (1.0f - (d + 12) * u);
-  const float gc = (d / 16 + 8) * u / (1.0f - (d / 16 + 8) * u);
+  return {(d + 12) * u / (1.0f - (d + 12) * u), (d / 16 + 8) * u / (1.0f - (d / 16 + 8) * u)};
+}
+
+template <int DK>
+__device__ __forceinline__ float screen_eps(float dt, ScreenGammas k, float E, float np, float nu) {
+  const float u = 5.9604645e-08f;  // 2^-24
+  const float gs = k.gs, gc = k.gc;
   float eps;
   if constexpr (DK == F32L2) {
     const float dd = dt > 0.0f ? dt : 0.0f;
@@ -247,35 +275,56 @@ __device__ __forceinline__ float screen_eps(float dt, int d, float E, float np, 
 // Screen the cnt new ids in ids_lds (cnt <= 256) against the beam's worst
 // exact distance w: ids that cannot enter the beam are dropped, the others
 // are compacted (in order) to the front of ids_lds.  Returns their number.
+// A narrow row is a quarter or half of the float32 row's bytes, so for rows
+// of fewer than 16 chunks per lane twice as many rows are kept in flight per
+// round as in the exact gathers (longer rows: one per group).  Every row's
+// loads of a round are issued before the first is used (with the loads
+// inside the per-row arithmetic the compiler waited on each row in turn, and
+// the screened harvest took 1.3-1.6x the plain one); lane g of a group loads
+// word g mod 4 of its row's trailer (err, norm, sinv, 0) with the codes, and
+// the group's lanes share those words by shuffles.
 template <int DK, int L, int NCH, int SCR>
 __device__ __forceinline__ int screen_filter(const BeamArgs& A, const Chunks<L, NCH>& a, float np,
                                              uint32_t* ids_lds, int cnt, float w) {
   constexpr int G = 64 / L;
-  constexpr int RB = (NCH >= 16) ? 1 : 16 / NCH;
+  constexpr int RB = (NCH >= 16) ? 1 : 32 / NCH;
+  static_assert(L >= 4, "a group holds the four trailer words");
   const int lane = lane_id();
   const int grp = lane / L, g = lane % L;
+  const int base = grp * L;
+  const ScreenGammas gam = screen_gammas(A.d);
   int kept = 0;
   for (int r0 = 0; r0 < cnt; r0 += G * RB) {
     uint32_t u[RB];
     float dt[RB];
+    float tw[RB];  // word g mod 4 of each row's trailer
+    NarrowChunks<NCH, SCR> rc[RB];
 #pragma unroll
     for (int t = 0; t < RB; t++) {
       const int r = r0 + t * G + grp;
       u[t] = ids_lds[r < cnt ? r : 0];
     }
+    // every row's loads are issued before any is used
 #pragma unroll
     for (int t = 0; t < RB; t++) {
-      const float sinv = SCR == SCR_FP8 ? A.xs_sinv[u[t]] : 1.0f;
-      dt[t] = group_screen<DK, L, NCH, SCR>(a, A.xs + (size_t)u[t] * A.xs_stride, sinv, A.Q, g);
+      const uint8_t* srow = A.xs + (size_t)u[t] * A.xs_stride;
+      load_narrow<L, NCH, SCR>(rc[t], srow, A.Q, g);
+      tw[t] = *reinterpret_cast<const float*>(srow + A.xs_tail + 4 * (g & 3));
+    }
+#pragma unroll
+    for (int t = 0; t < RB; t++) {
+      const float sinv = SCR == SCR_FP8 ? __shfl(tw[t], base + 2, 64) : 1.0f;
+      dt[t] = group_screen<DK, L, NCH, SCR>(a, rc[t], sinv, A.Q, g);
     }
     wave_sync();
 #pragma unroll
     for (int t = 0; t < RB; t++) {
       const int r = r0 + t * G + grp;
+      const float err = __shfl(tw[t], base, 64);
+      const float nu = DK == F32COS ? __shfl(tw[t], base + 1, 64) : 0.0f;
       bool keep = false;
       if (r < cnt && g == 0) {
-        const float nu = DK == F32COS ? A.xs_norm[u[t]] : 0.0f;
-        const float eps = screen_eps<DK>(dt[t], A.d, A.xs_err[u[t]], np, nu);
+        const float eps = screen_eps<DK>(dt[t], gam, err, np, nu);
         keep = !(dt[t] - eps > w);
       }
       const uint64_t m = ballot(keep);
@@ -907,7 +956,8 @@ k_beam(BeamArgs A) {
     uint32_t qn = 0;
     if constexpr (DK == U8L2) qn = group_sum_u32<L>(u8_selfdot<L, NCH>(qc));
     float qnorm = 0.0f;  // |p| for the cosine screen margin
-    if constexpr (SCR != SCR_NONE && DK == F32COS) qnorm = A.xs_norm[p];
+    if constexpr (SCR != SCR_NONE && DK == F32COS)
+      qnorm = reinterpret_cast<const float4*>(A.xs + (size_t)p * A.xs_stride + A.xs_tail)->y;
 
     for (int i = lane; i < HSLOTS; i += 64) S.htab[i] = FG_NONE;
     if (lane == 0) S.nspill = 0;
@@ -1033,6 +1083,7 @@ k_beam(BeamArgs A) {
             const int nx = screen_filter<DK, L, NCH, SCR>(A, qc, qnorm, S.sid, nnew, w);
             my_rej += (unsigned long long)(nnew - nx);
             nnew = nx;
+            FG_TICK(8);
             if (nnew == 0) continue;
           }
         }

@@ -60,10 +60,14 @@ void* pick_screen_bf16(int dk, int Q, int ef, int hslots);
 void* pick_screen_fp8(int dk, int Q, int ef, int hslots);
 
 // Narrow copies for the screened harvest (fg_screen.hip): row stride in
-// bytes, and the copy with its per-row error norm, norm and fp8 factor.
+// bytes (whole 128-byte lines), the offset of each row's 16-byte trailer
+// (float err, norm, sinv, 0) after its codes, and the copy with its per-row
+// error norm, norm and fp8 factor.
 int64_t screen_stride(int d, int screen);
-// xs may be NULL (no plain copy); sp (bfloat16 only, may be NULL) receives
-// the interleaved hi/lo split, rows split_stride(d) bytes apart.
+int64_t screen_tail(int d, int screen);
+// xs may be NULL (no plain copy), and so may err, norm and sinv (the
+// trailers hold them); sp (bfloat16 only, may be NULL) receives the
+// interleaved hi/lo split, rows split_stride(d) bytes apart.
 int64_t split_stride(int d);
 // |x_i|^2 of every float32 row (fg_sat.hip).
 hipError_t row_sq_norms(const Shape& s, float* out, hipStream_t st);

@@ -73,6 +73,25 @@ def test_screen_copy_bf16_is_rne_with_true_error_norms():
     assert np.all(e_gpu >= e_true) and np.all(e_gpu <= _loosest(e_true, x))
     assert np.all(n_gpu >= n_true) and np.all(n_gpu <= _loosest(n_true, x))
     assert np.all(sinv.cpu().numpy() == 1.0)
+    _check_row_layout(F, xs, err, nrm, sinv, d, F.SCREEN_BF16)
+
+
+def _check_row_layout(F, xs, err, nrm, sinv, d, screen):
+    """Rows are whole 128-byte lines; after the codes (padded to 16-element
+    steps for bfloat16, 16 bytes for fp8) each holds the trailer
+    (err, norm, sinv, 0), and bfloat16 rows are zero everywhere else."""
+    rb = xs.shape[1]
+    assert rb % 128 == 0
+    tail = (2 * d + 31) // 32 * 32 if screen == F.SCREEN_BF16 else (d + 15) // 16 * 16
+    assert tail + 16 <= rb < tail + 16 + 128
+    host = xs.cpu().numpy()
+    tr = host[:, tail:tail + 16].copy().view(np.float32)
+    assert np.array_equal(tr[:, 0], err.cpu().numpy())
+    assert np.array_equal(tr[:, 1], nrm.cpu().numpy())
+    assert np.array_equal(tr[:, 2], sinv.cpu().numpy())
+    assert np.all(tr[:, 3] == 0.0)
+    if screen == F.SCREEN_BF16:
+        assert not host[:, 2 * d:tail].any() and not host[:, tail + 16:].any()
 
 
 def test_screen_copy_fp8_codes_decode_per_ocp_e4m3():
@@ -107,6 +126,7 @@ def test_screen_copy_fp8_codes_decode_per_ocp_e4m3():
     e_true = np.sqrt(((back - xd) ** 2).sum(1))
     e_gpu = err.cpu().numpy().astype(np.float64)
     assert np.all(e_gpu >= e_true) and np.all(e_gpu <= _loosest(e_true, x))
+    _check_row_layout(F, xs, err, nrm, sinv, d, F.SCREEN_FP8E4M3)
 
 
 SCREEN_BUILDS = [
