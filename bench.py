@@ -114,7 +114,10 @@ def dsweep(args):
     truncated to each d."""
     n = args.n or 200_000
     out = []
-    for i, d in enumerate((32, 64, 128, 256, 512, 960)):
+    all_dims = (32, 64, 128, 256, 512, 960)
+    dims = [int(v) for v in args.dims.split(",")] if args.dims else list(all_dims)
+    for d in dims:
+        i = all_dims.index(d)  # the draw's seed follows d's place in the full sweep
         x = gen.powerlaw_f32(n, d, 500, 40 + i, d_total=960)
         xd = torch.from_numpy(x).cuda()
         data = F.make_data(xd)
@@ -154,7 +157,8 @@ def dsweep(args):
         torch.cuda.empty_cache()
     ds = np.log([r["d"] for r in out])
     fit = {k: float(np.polyfit(ds, np.log([r[k] for r in out]), 1)[0])
-           for k in ("adaptive_ns_per_eval", "blocked_fp32_ns_per_pair", "blocked_bf16_ns_per_pair", "W_fp32")}
+           for k in ("adaptive_ns_per_eval", "blocked_fp32_ns_per_pair", "blocked_bf16_ns_per_pair", "W_fp32")
+           } if len(out) >= 2 else None
     print(json.dumps({"mode": "dsweep", "n": n, "rows": out, "loglog_exponents": fit}), flush=True)
 
 
@@ -686,16 +690,21 @@ def batched_compare(args):
 
     ws_b = None
 
-    def batched(use_graph):
+    def batched(use_graph, tune=False):
         nonlocal ws_b
-        c, ws_b = F.build_graph_batched(datas, params, seeds, graphs, ws=ws_b, use_hipgraph=use_graph)
+        c, ws_b = F.build_graph_batched(datas, params, seeds, graphs, ws=ws_b, use_hipgraph=use_graph,
+                                        autotune=tune)
         return c["harvest_evals"]
 
-    runs = {"sequential": sequential, "batched": lambda: batched(False), "batched_hipgraph": lambda: batched(True)}
+    # the autotuned forms tune on their first call (block 0 of the batch over
+    # the scaffold) and reuse the cached choice afterwards
+    runs = {"sequential": sequential, "batched": lambda: batched(False), "batched_hipgraph": lambda: batched(True),
+            "batched_autotune": lambda: batched(False, True),
+            "batched_hipgraph_autotune": lambda: batched(True, True)}
     # warm-up and hash check
     sequential()
     want = [F.graph_hash(g) for g in graphs]
-    for name in ("batched", "batched_hipgraph"):
+    for name in [k for k in runs if k != "sequential"]:
         runs[name]()
         got = [F.graph_hash(g) for g in graphs]
         assert got == want, name
@@ -747,6 +756,7 @@ def main():
     ap.add_argument("--workloads", default="cfg3,cfg4", help="screen mode: cfg3, cfg4 or both")
     ap.add_argument("--reps", type=int, default=3, help="screen mode: paired repetitions; wsweep: timed builds per prefix")
     ap.add_argument("--sizes", default="", help="wsweep mode: comma-separated prefix sizes")
+    ap.add_argument("--dims", default="", help="dsweep mode: a subset of 32,64,128,256,512,960")
     ap.add_argument("--sweep-workload", default="glove", choices=("glove", "u8", "gist"),
                     help="wsweep mode: the GloVe-shaped float32 rows, the benchmark line's uint8 rows "
                          "or the GIST-shaped float32 rows")
@@ -762,6 +772,8 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override n (default: the workload's)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the screened builds and the batched comparison after the line")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="rows of the oracle's sample build (0: 50,000 for the GloVe-shaped "
                          "workload, 300,000 otherwise)")
@@ -898,6 +910,73 @@ def run_builds(key, w, args, steps, warmup, xd=None, x=None):
     return rec, dict(x=x, xd=xd, data=data, G=G, ws=ws, metric=metric, wall=wall)
 
 
+def forms_vs_fp32(key, w, st):
+    """The precision form beside the plain one on the benchmark line's data:
+    one warm-up and one timed build per screened form (its own workspace,
+    the narrow copy included); the graph hash must equal the plain build's."""
+    data, G, base = st["data"], st["G"], F.graph_hash(st["G"])
+    out = {}
+    if w.dtype != "f32" or w.d <= 64:
+        return out
+    for f, name in ((F.SCREEN_FP8E4M3, "fp8e4m3"), (F.SCREEN_BF16, "bf16")):
+        params = F.make_params(w.T, w.ef_h, w.R, w.alpha, w.B, screen=f)
+        ws = F.alloc_workspace(data, params)
+        F.build_graph(data, w.build_seed, params, G, ws, timings=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c, t = F.build_graph(data, w.build_seed, params, G, ws, timings=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        assert F.graph_hash(G) == base, name
+        out[name] = {"harvest_ms": t["harvest_ms"], "build_s": wall,
+                     "screen_rejected_frac": c["screen_rejected"] / c["harvest_evals"]}
+        log(f"[bench] {key} screen {name}: harvest {t['harvest_ms']:.1f} ms build {wall:.2f} s")
+        del ws
+        torch.cuda.empty_cache()
+    return out
+
+
+def batched_vs_sequential():
+    """The batched form on its workload (64 uneven float32 instances, 3.1 M
+    points): 64 sequential builds against one autotuned batched build with
+    the blocks in one HIP graph, each after a warm-up; every instance's
+    hash must equal its sequential build's."""
+    insts = gen.batched_instances(count=64, scale=1.0)
+
+    def u32(*shape):
+        return torch.full(shape, -1, dtype=torch.int32, device="cuda")
+
+    datas, params, graphs = [], [], []
+    for i in insts:
+        n = i["x"].shape[0]
+        datas.append(F.make_data(torch.from_numpy(i["x"]).cuda()))
+        params.append(F.make_params(i["T"], i["ef_h"], i["R"], i["alpha"], i["B"]))
+        graphs.append(F.make_graph(u32(n, i["R"]), u32(n), u32(n), u32(i["T"]), i["T"]))
+    seeds = [i["seed"] for i in insts]
+    big = max(range(len(insts)), key=lambda k: insts[k]["x"].shape[0])
+    ws_seq = F.alloc_workspace(datas[big], F.make_params(8, 128, 32, 1.2, 8))
+    res, ws_b = {}, None
+    for rep in range(2):  # the first pass of each is the warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(len(insts)):
+            F.build_graph(datas[k], seeds[k], params[k], graphs[k], ws_seq)
+        torch.cuda.synchronize()
+        res["sequential_s"] = time.perf_counter() - t0
+        want = [F.graph_hash(g) for g in graphs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, ws_b = F.build_graph_batched(datas, params, seeds, graphs, ws=ws_b, use_hipgraph=True, autotune=True)
+        torch.cuda.synchronize()
+        res["batched_s"] = time.perf_counter() - t0
+        assert [F.graph_hash(g) for g in graphs] == want
+    res["speedup"] = res["sequential_s"] / res["batched_s"]
+    res["instances"] = len(insts)
+    res["points"] = int(sum(i["x"].shape[0] for i in insts))
+    log(f"[bench] batched: {res}")
+    return res
+
+
 def headline(args):
     """The benchmark line: whole builds of the GloVe-shaped workload
     (n = 1,183,514, d = 100, unit float32 rows, cosine; T=8 B=8 ef_h=128
@@ -943,6 +1022,8 @@ def headline(args):
     }
     if "oracle_full_size" in rec:
         out["oracle_full_size"] = rec["oracle_full_size"]
+    if not args.no_forms:
+        out["forms_vs_fp32"] = forms_vs_fp32(key, w, st)
     if args.calib_copy:
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         a.fill_(1)
@@ -971,6 +1052,8 @@ def headline(args):
         n_cpu = args.cpu_sample or (50_000 if w is gen.CFG3 else 300_000)
         log(f"[bench] cpu baseline: oracle on {n_cpu} points, {threads} threads")
         out["cpu_baseline"] = cpu_baseline(w, n_cpu, threads)
+    if not args.no_forms:
+        out["batched_vs_sequential"] = batched_vs_sequential()
     extra = [k for k in args.extra.split(",") if k and k != key]
     if extra:
         out["extra_workloads"] = {}
