@@ -737,16 +737,80 @@ def batched_compare(args):
     print(json.dumps(out), flush=True)
 
 
+def recheck_rates(args):
+    """Share of the occlusion prune's kill tests, alpha d(r, c) <= d(p, c),
+    that a tile form's proven margin leaves undecided (each one an exact
+    recheck), measured on the host in float64 over sampled points of a
+    workload: each point's 128 nearest candidates pruned in distance order
+    (R = 64, alpha = 1.2) and every test the prune makes.  Forms: the
+    float32 tiles and the bf16 split on the rows as stored, and single bf16
+    or fp8 operands on candidates centred on the point (c - p), whose
+    product error is (2u + u^2) |a'| |c'| with u = 2^-8 / 2^-4."""
+    names = {"cfg3": gen.CFG3, "cfg4": gen.CFG4}
+    out = {"mode": "recheck", "rows": []}
+    for key in args.workloads.split(","):
+        w = names[key]
+        n = args.n or 200_000
+        x = gen.workload_data(w, n).astype(np.float32)
+        X = torch.from_numpy(x).double()
+        rng = np.random.default_rng(5)
+        P = rng.choice(n, 300, replace=False)
+        d, M, R, alpha, u = x.shape[1], 128, 64, 1.2, 2.0 ** -24
+        gg = (d + 4) * 2 * u
+        tot = {"tests": 0, "f32": 0, "bf16_split": 0, "bf16_centred": 0, "fp8_centred": 0}
+        xn2 = (X * X).sum(1)
+        for p in P:
+            q = X[p]
+            dist = 1.0 - X @ q if w.metric == "cosine" else xn2 - 2 * X @ q + xn2[p]
+            dist[p] = np.inf
+            idx = torch.topk(dist, M, largest=False).indices.numpy()
+            C, dpc = X[idx], dist[idx].numpy()
+            nc = np.linalg.norm((C - q).numpy(), axis=1)
+            nraw = np.linalg.norm(C.numpy(), axis=1)
+            if w.metric == "cosine":
+                Dcc = 1.0 - (C @ C.T).numpy()
+            else:
+                Gm = (C @ C.T).numpy()
+                Dcc = np.diag(Gm)[:, None] + np.diag(Gm)[None, :] - 2 * Gm
+            alive, kept = np.ones(M, bool), 0
+            for i in range(M):
+                if not alive[i]:
+                    continue
+                kept += 1
+                if kept >= R:
+                    break
+                js = np.nonzero(alive[i + 1:])[0] + i + 1
+                t = np.abs(alpha * Dcc[i, js] - dpc[js])
+                tot["tests"] += len(js)
+                if w.metric == "cosine":
+                    m32 = 2 * (gg + 2 * u) * nraw[i] * nraw[js]
+                    msp = 2 * (3.1 * 2.0 ** -16 + gg) * nraw[i] * nraw[js]
+                else:
+                    m32 = 4 * (gg + 2 * u) * (nraw[i] ** 2 + nraw[js] ** 2)
+                    msp = 4 * (3.1 * 2.0 ** -16 + gg) * (nraw[i] ** 2 + nraw[js] ** 2)
+                mbf = 4 * (2 * 2.0 ** -8 + 2.0 ** -16 + gg) * nc[i] * nc[js]
+                mf8 = 4 * (2 * 2.0 ** -4 + 2.0 ** -8 + gg) * nc[i] * nc[js]
+                for k, m in (("f32", m32), ("bf16_split", msp), ("bf16_centred", mbf), ("fp8_centred", mf8)):
+                    tot[k] += int((t <= alpha * m).sum())
+                alive[js[alpha * Dcc[i, js] <= dpc[js]]] = False
+        row = {"workload": w.name, "sample_rows": n, "points": len(P), "tests": tot["tests"]}
+        row.update({f"undecided_{k}": tot[k] / tot["tests"] for k in tot if k != "tests"})
+        log(f"[recheck] {row}")
+        out["rows"].append(row)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--mode", default="build",
-                    choices=("build", "dsweep", "screen", "batched", "wsweep", "quality", "density"),
+                    choices=("build", "dsweep", "screen", "batched", "wsweep", "quality", "density", "recheck"),
                     help="build: the benchmark line (default); dsweep: wall vs dimension; "
                          "screen: bf16 / fp8 screened builds against float32; "
                          "batched: 64 instances built together against sequential builds; "
                          "wsweep: throughput against working set (GloVe-shaped prefixes); "
                          "quality: completeness, recall ladder and d@r for T/B arms; "
-                         "density: lockstep density of coherent and random blocks (visit log)")
+                         "density: lockstep density of coherent and random blocks (visit log); "
+                         "recheck: share of prune tests a tile form's margin leaves undecided (host only)")
     ap.add_argument("--density-workload", default="glove", choices=("glove", "u8"),
                     help="density mode: the GloVe-shaped float32 rows or the SIFT-shaped uint8 rows")
     ap.add_argument("--log-cap", type=int, default=131072,
@@ -809,6 +873,8 @@ def main():
         return quality(args)
     if args.mode == "density":
         return density(args)
+    if args.mode == "recheck":
+        return recheck_rates(args)
 
     return headline(args)
 

@@ -726,22 +726,28 @@ __device__ __forceinline__ float gram_eps(float dt, float gaa, float gcc, int d,
   float gg = nk * (2.0f * u) / (1.0f - nk * (2.0f * u));
   if (split) gg = 3.1f * 1.5258789e-05f + 1.016f * gg;
   const float gc = (d / 16 + 8) * u / (1.0f - (d / 16 + 8) * u);
+  const float sn = fabsf(gaa) + fabsf(gcc);
   float eps;
   if constexpr (DK == F32L2) {
-    const float s2 = 2.0f * (fabsf(gaa) + fabsf(gcc)) / (1.0f - gg);
+    const float s2 = 2.0f * sn / (1.0f - gg);
     const float b = (gg + 2.0f * u) * (1.0f + gg) * s2;
     eps = b + gc * (fabsf(dt) + b);
   } else {
     const float nn = __builtin_sqrtf(fabsf(gaa) * fabsf(gcc)) / (1.0f - gg);
     eps = (gg + gc) * nn + 4.0f * u * (1.0f + nn);
   }
-  const float na = __builtin_sqrtf(fabsf(gaa) + 7.5231638e-37f);  // 2^-120
-  const float nc = __builtin_sqrtf(fabsf(gcc) + 7.5231638e-37f);
-  const float flushed = (split ? 3.0f : 1.0f) * __builtin_sqrtf((float)d) * (na + nc);
-  if constexpr (DK == F32L2)
-    eps += 4.7019774e-38f * (flushed + 2.0f * (float)nk);  // 2^-124
-  else
-    eps += 2.3509887e-38f * (flushed + (float)nk);  // 2^-125
+  // Underflow: flushed operands contribute at most 2^-126 sqrt(d) (|a| + |c|)
+  // per product plane (k planes), bounded without roots by
+  // sqrt(d) sqrt(y) <= (d + y) / 2 with y = |G| + 2^-120, and nk flushed or
+  // underflowed partial results at most 2^-126 each (twice for L2's 2 G_ac):
+  //   L2: 2^-124 (k (d + sn / 2 + 2^-120) + 2 nk), cosine: 2^-125 (k (...) + nk),
+  // written as c1 sn + c0 with c0, c1 fixed by d (a square root per pair
+  // here cost the 10^6 x 960 scaffold a tenth of its time).
+  const float kf = split ? 3.0f : 1.0f;
+  const float sc = DK == F32L2 ? 4.7019774e-38f : 2.3509887e-38f;  // 2^-124, 2^-125
+  const float c0 = sc * (kf * ((float)d + 7.5231638e-37f) + (DK == F32L2 ? 2.0f : 1.0f) * (float)nk);
+  const float c1 = sc * kf * 0.5f;
+  eps += __builtin_fmaf(c1, sn, c0);
   return 2.0f * eps;
 }
 

@@ -23,5 +23,5 @@ def test_more_than_one_gpu_is_refused():
 def test_modes_are_listed():
     r = _run("--help")
     assert r.returncode == 0
-    for mode in ("build", "dsweep", "screen", "batched", "wsweep", "quality"):
+    for mode in ("build", "dsweep", "screen", "batched", "wsweep", "quality", "density", "recheck"):
         assert mode in r.stdout

@@ -26,9 +26,10 @@ def margin(dt, gaa, gcc, d, metric, split):
         nn = np.sqrt(abs(gaa) * abs(gcc)) / (1 - gg)
         eps = (gg + gc) * nn + 4 * U * (1 + nn)
     # underflow: flushed operands (k products per element) and nk flushed or
-    # underflowed partial results, at most 2^-126 each
-    na, nc = np.sqrt(abs(gaa) + 2.0 ** -120), np.sqrt(abs(gcc) + 2.0 ** -120)
-    flushed = (3 if split else 1) * np.sqrt(d) * (na + nc)
+    # underflowed partial results, at most 2^-126 each; the operands' term
+    # 2^-126 sqrt(d) (|a| + |c|) is bounded by AM-GM,
+    # sqrt(d) sqrt(y) <= (d + y) / 2 with y = |G| + 2^-120
+    flushed = (3 if split else 1) * (d + 0.5 * (abs(gaa) + abs(gcc)) + 2.0 ** -120)
     if metric == "l2":
         eps += 2.0 ** -124 * (flushed + 2 * nk)
     else:
@@ -170,3 +171,17 @@ def test_split_planes_carry_sixteen_bits():
     hi, lo = bf16_split(x)
     r = np.abs(x.astype(np.float64) - hi.astype(np.float64) - lo.astype(np.float64))
     assert np.all(r <= 2.0 ** -16 * np.abs(x.astype(np.float64)))
+
+
+@pytest.mark.parametrize("d", [68, 260, 960])
+def test_flush_term_dominates_operand_flush_bound(d):
+    """The margin's operand-flush term, d + (|G_aa| + |G_cc|) / 2 + 2^-120,
+    is at least sqrt(d) (sqrt(|G_aa| + 2^-120) + sqrt(|G_cc| + 2^-120)),
+    the bound on sum_i |a_i c_i| over operands flushed below 2^-126 (per
+    unit of 2^-126), for squared norms across the float32 range."""
+    g = np.concatenate([[0.0], np.logspace(-45, 38, 400)])
+    ga, gc = np.meshgrid(g, g)
+    t = 2.0 ** -120
+    root_form = np.sqrt(d) * (np.sqrt(ga + t) + np.sqrt(gc + t))
+    amgm = d + 0.5 * (ga + gc) + t
+    assert np.all(amgm >= root_form * (1 - 1e-12))
