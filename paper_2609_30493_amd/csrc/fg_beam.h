@@ -194,9 +194,13 @@ __device__ __forceinline__ void load_narrow(NarrowChunks<NCH, SCR>& r, const uin
   }
 }
 
-// Screened distance between the query's exact float32 chunks `a` and a
-// narrow row's chunks, reduced over the group.  Any summation order: the
-// margin below holds for all of them.
+// Screened sum between the query's exact float32 chunks `a` and a narrow
+// row's chunks, reduced over the group (every lane of the group gets it):
+// squared L2, the codes scaled by sinv element by element; cosine, the dot
+// product with the unscaled codes (the caller forms 1 - sinv * sum: a power
+// of two commutes with every rounding of the sum, and an overflow can only
+// make the caller keep the candidate).  Any summation order: the margin
+// below holds for all of them.
 template <int DK, int L, int NCH, int SCR>
 __device__ __forceinline__ float group_screen(const Chunks<L, NCH>& a, const NarrowChunks<NCH, SCR>& r, float sinv,
                                               int Q, int g) {
@@ -215,7 +219,10 @@ __device__ __forceinline__ float group_screen(const Chunks<L, NCH>& a, const Nar
         const int w = (int)r.w[i];
         const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8(w, false);
         const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8(w, true);
-        xb = make_float4(lo[0] * sinv, lo[1] * sinv, hi[0] * sinv, hi[1] * sinv);
+        if constexpr (DK == F32L2)
+          xb = make_float4(lo[0] * sinv, lo[1] * sinv, hi[0] * sinv, hi[1] * sinv);
+        else
+          xb = make_float4(lo[0], lo[1], hi[0], hi[1]);
       }
       if constexpr (DK == F32L2) {
         const float d0 = xa.x - xb.x, d1 = xa.y - xb.y, d2 = xa.z - xb.z, d3 = xa.w - xb.w;
@@ -233,7 +240,6 @@ __device__ __forceinline__ float group_screen(const Chunks<L, NCH>& a, const Nar
   }
 #pragma unroll
   for (int off = L / 2; off >= 1; off >>= 1) acc = acc + __shfl_xor(acc, off, 64);
-  if constexpr (DK == F32COS) acc = 1.0f - acc;
   return acc;
 }
 
@@ -274,21 +280,23 @@ __device__ __forceinline__ float screen_eps(float dt, ScreenGammas k, float E, f
 
 // Screen the cnt new ids in ids_lds (cnt <= 256) against the beam's worst
 // exact distance w: ids that cannot enter the beam are dropped, the others
-// are compacted (in order) to the front of ids_lds.  Returns their number.
-// A narrow row is a quarter or half of the float32 row's bytes, so for rows
-// of fewer than 16 chunks per lane twice as many rows are kept in flight per
-// round as in the exact gathers (longer rows: one per group).  Every row's
-// loads of a round are issued before the first is used (with the loads
-// inside the per-row arithmetic the compiler waited on each row in turn, and
-// the screened harvest took 1.3-1.6x the plain one); lane g of a group loads
-// word g mod 4 of its row's trailer (err, norm, sinv, 0) with the codes, and
-// the group's lanes share those words by shuffles.
+// are compacted to the front of ids_lds (in an order of their own: the
+// beam's merge sorts by key).  Returns their number.  A narrow row is a
+// quarter or half of the float32 row's bytes, so for rows of fewer than 16
+// chunks per lane twice as many rows are kept in flight per round as in
+// the exact gathers (longer rows: one per group).  Every row's loads of a
+// round are issued before the first is used (with the loads inside the
+// per-row arithmetic the compiler waited on each row in turn, and the
+// screened harvest took 1.3-1.6x the plain one).  Lane g of a group owns
+// row g of the group's rows in the round: it loads that row's trailer
+// (err, norm, sinv) and decides it, so one ballot per round compacts the
+// survivors.
 template <int DK, int L, int NCH, int SCR>
 __device__ __forceinline__ int screen_filter(const BeamArgs& A, const Chunks<L, NCH>& a, float np,
                                              uint32_t* ids_lds, int cnt, float w) {
   constexpr int G = 64 / L;
   constexpr int RB = (NCH >= 16) ? 1 : 32 / NCH;
-  static_assert(L >= 4, "a group holds the four trailer words");
+  static_assert(RB <= L, "a lane owns at most one row of a round");
   const int lane = lane_id();
   const int grp = lane / L, g = lane % L;
   const int base = grp * L;
@@ -297,40 +305,37 @@ __device__ __forceinline__ int screen_filter(const BeamArgs& A, const Chunks<L, 
   for (int r0 = 0; r0 < cnt; r0 += G * RB) {
     uint32_t u[RB];
     float dt[RB];
-    float tw[RB];  // word g mod 4 of each row's trailer
     NarrowChunks<NCH, SCR> rc[RB];
 #pragma unroll
     for (int t = 0; t < RB; t++) {
       const int r = r0 + t * G + grp;
       u[t] = ids_lds[r < cnt ? r : 0];
     }
+    const int myr = r0 + g * G + grp;
+    const bool mine = g < RB && myr < cnt;
+    const uint32_t myid = ids_lds[mine ? myr : 0];
     // every row's loads are issued before any is used
+    const float4 tr = *reinterpret_cast<const float4*>(A.xs + (size_t)myid * A.xs_stride + A.xs_tail);
+#pragma unroll
+    for (int t = 0; t < RB; t++) load_narrow<L, NCH, SCR>(rc[t], A.xs + (size_t)u[t] * A.xs_stride, A.Q, g);
 #pragma unroll
     for (int t = 0; t < RB; t++) {
-      const uint8_t* srow = A.xs + (size_t)u[t] * A.xs_stride;
-      load_narrow<L, NCH, SCR>(rc[t], srow, A.Q, g);
-      tw[t] = *reinterpret_cast<const float*>(srow + A.xs_tail + 4 * (g & 3));
-    }
-#pragma unroll
-    for (int t = 0; t < RB; t++) {
-      const float sinv = SCR == SCR_FP8 ? __shfl(tw[t], base + 2, 64) : 1.0f;
+      // squared L2 over fp8 codes scales each element by its row's factor,
+      // which lane t of the group loaded
+      const float sinv = (SCR == SCR_FP8 && DK == F32L2) ? __shfl(tr.z, base + t, 64) : 1.0f;
       dt[t] = group_screen<DK, L, NCH, SCR>(a, rc[t], sinv, A.Q, g);
     }
-    wave_sync();
+    float own = dt[0];
 #pragma unroll
-    for (int t = 0; t < RB; t++) {
-      const int r = r0 + t * G + grp;
-      const float err = __shfl(tw[t], base, 64);
-      const float nu = DK == F32COS ? __shfl(tw[t], base + 1, 64) : 0.0f;
-      bool keep = false;
-      if (r < cnt && g == 0) {
-        const float eps = screen_eps<DK>(dt[t], gam, err, np, nu);
-        keep = !(dt[t] - eps > w);
-      }
-      const uint64_t m = ballot(keep);
-      if (keep) ids_lds[kept + popc64(m & lanes_below())] = u[t];
-      kept += popc64(m);
-    }
+    for (int t = 1; t < RB; t++)
+      if (g == t) own = dt[t];
+    if constexpr (DK == F32COS) own = 1.0f - (SCR == SCR_FP8 ? tr.z * own : own);
+    const float eps = screen_eps<DK>(own, gam, tr.x, np, DK == F32COS ? tr.y : 0.0f);
+    const bool keep = mine && !(own - eps > w);
+    wave_sync();  // every read of this round's ids precedes the compaction
+    const uint64_t m = ballot(keep);
+    if (keep) ids_lds[kept + popc64(m & lanes_below())] = myid;
+    kept += popc64(m);
     wave_sync();
   }
   return kept;
