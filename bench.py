@@ -176,13 +176,13 @@ def wsweep(args):
     blocked kernel on a float32 copy of the rows.  With --sweep-workload gist
     the GIST-shaped float32 rows (d = 960, 3840 B, T=8 B=8 ef_h=128 R=64),
     25,000 to 1,000,000 rows (96 MB to 3.8 GB)."""
-    w = {"u8": gen.CFG2, "gist": gen.CFG4}.get(args.sweep_workload, gen.CFG3)
-    default = {id(gen.CFG2): [250_000, 500_000, 1_000_000, 2_000_000, 4_000_000],
-               id(gen.CFG4): [25_000, 50_000, 100_000, 200_000, 500_000, 1_000_000]}.get(
+    w = {"u8": gen.SIFT_1M, "gist": gen.GIST_1M}.get(args.sweep_workload, gen.GLOVE_1183514)
+    default = {id(gen.SIFT_1M): [250_000, 500_000, 1_000_000, 2_000_000, 4_000_000],
+               id(gen.GIST_1M): [25_000, 50_000, 100_000, 200_000, 500_000, 1_000_000]}.get(
         id(w), [20_000, 50_000, 100_000, 200_000, 500_000, w.n])
     sizes = [int(v) for v in args.sizes.split(",")] if args.sizes else default
     metric = "cosine" if w.metric == "cosine" else "l2"
-    table = 1024 if w is gen.CFG2 else 0
+    table = 1024 if w is gen.SIFT_1M else 0
     N = max(sizes)
     log(f"[wsweep] generating {N} x {w.d} rows ({w.recipe})")
     x = gen.workload_data(w, N)
@@ -409,7 +409,7 @@ def density(args):
     sum |V_i| / (B |U V_i|), the share of expansion-1..10 evaluations that
     adjacent points share, and the share of evaluations whose target at least
     eight points of the block evaluate."""
-    w = gen.CFG2 if args.density_workload == "u8" else gen.CFG3
+    w = gen.SIFT_1M if args.density_workload == "u8" else gen.GLOVE_1183514
     n = args.n or w.n
     metric = "cosine" if w.metric == "cosine" else "l2"
     log(f"[density] generating {n} x {w.d} rows ({w.recipe})")
@@ -476,7 +476,7 @@ def quality(args):
     at each beam width, and d@0.95 / d@0.97 against the first arm.  With
     --quality-workload gist the same on the GIST-shaped rows (d = 960, L2,
     1,000 held-out queries)."""
-    w = gen.CFG4 if args.quality_workload == "gist" else gen.CFG3
+    w = gen.GIST_1M if args.quality_workload == "gist" else gen.GLOVE_1183514
     n = args.n or w.n
     metric = "cosine" if w.metric == "cosine" else "l2"
     arms = [tuple(int(v) for v in a.split(":")) for a in args.arms.split(",")]
@@ -569,7 +569,7 @@ def screen_compare(args):
     estimate over repetitions and the exact Wilcoxon signed-rank p."""
     from scipy import stats
     rows = []
-    names = {"cfg3": gen.CFG3, "cfg4": gen.CFG4}
+    names = {"glove": gen.GLOVE_1183514, "gist": gen.GIST_1M}
     for key in args.workloads.split(","):
         w = names[key]
         n = args.n or w.n
@@ -658,7 +658,7 @@ def screen_compare(args):
 
 
 def batched_compare(args):
-    """Batched form (cfg5): 64 uneven instances built together -- eager, and
+    """Batched form (the 64-instance workload): 64 uneven instances built together -- eager, and
     with the blocks captured in one HIP graph -- against 64 sequential
     build_graph calls, paired repetitions in seeded random order; every
     instance's graph hash must equal its sequential build's."""
@@ -746,7 +746,7 @@ def recheck_rates(args):
     float32 tiles and the bf16 split on the rows as stored, and single bf16
     or fp8 operands on candidates centred on the point (c - p), whose
     product error is (2u + u^2) |a'| |c'| with u = 2^-8 / 2^-4."""
-    names = {"cfg3": gen.CFG3, "cfg4": gen.CFG4}
+    names = {"glove": gen.GLOVE_1183514, "gist": gen.GIST_1M}
     out = {"mode": "recheck", "rows": []}
     for key in args.workloads.split(","):
         w = names[key]
@@ -817,7 +817,7 @@ def main():
                     help="density mode: visited ids kept per logged point")
     ap.add_argument("--instances", type=int, default=64, help="batched mode: instance count")
     ap.add_argument("--scale", type=float, default=1.0, help="batched mode: shrink every instance's n")
-    ap.add_argument("--workloads", default="cfg3,cfg4", help="screen mode: cfg3, cfg4 or both")
+    ap.add_argument("--workloads", default="glove,gist", help="screen mode: glove, gist or both")
     ap.add_argument("--reps", type=int, default=3, help="screen mode: paired repetitions; wsweep: timed builds per prefix")
     ap.add_argument("--sizes", default="", help="wsweep mode: comma-separated prefix sizes")
     ap.add_argument("--dims", default="", help="dsweep mode: a subset of 32,64,128,256,512,960")
@@ -841,11 +841,11 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="rows of the oracle's sample build (0: 50,000 for the GloVe-shaped "
                          "workload, 300,000 otherwise)")
-    ap.add_argument("--workload", default="cfg3", choices=tuple(WORKLOADS),
-                    help="the benchmark line's workload: cfg3 the GloVe-shaped float32 cosine "
-                         "build (default), cfg2 the SIFT-shaped uint8 build, cfg4 the GIST-shaped "
+    ap.add_argument("--workload", default="glove", choices=tuple(WORKLOADS),
+                    help="the benchmark line's workload: glove the GloVe-shaped float32 cosine "
+                         "build (default), sift the SIFT-shaped uint8 build, gist the GIST-shaped "
                          "d = 960 build")
-    ap.add_argument("--extra", default="cfg2,cfg4",
+    ap.add_argument("--extra", default="sift,gist",
                     help="other full-size workloads measured once each after the line (extra keys)")
     ap.add_argument("--table", type=int, default=0, choices=(0, 512, 1024, 2048, 4096),
                     help="on-chip visited-table slots per search (0 = library default)")
@@ -879,11 +879,11 @@ def main():
     return headline(args)
 
 
-WORKLOADS = {"cfg3": gen.CFG3, "cfg2": gen.CFG2, "cfg4": gen.CFG4}
+WORKLOADS = {"glove": gen.GLOVE_1183514, "sift": gen.SIFT_1M, "gist": gen.GIST_1M}
 # the dominant kernel's counter summaries (two rocprofv3 --pmc passes of this
 # script's default run), one per workload
-PMC_SUMMARIES = {"cfg3": os.path.join(ROOT, "profiles", "k_beam_harvest_f32_cosine_1183514_pmc.md"),
-                 "cfg2": PMC_SUMMARY}
+PMC_SUMMARIES = {"glove": os.path.join(ROOT, "profiles", "k_beam_harvest_f32_cosine_1183514_pmc.md"),
+                 "sift": PMC_SUMMARY}
 
 
 def oracle_golden(key: str):
@@ -1115,7 +1115,7 @@ def headline(args):
     torch.cuda.empty_cache()
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)
-        n_cpu = args.cpu_sample or (50_000 if w is gen.CFG3 else 300_000)
+        n_cpu = args.cpu_sample or (50_000 if w is gen.GLOVE_1183514 else 300_000)
         log(f"[bench] cpu baseline: oracle on {n_cpu} points, {threads} threads")
         out["cpu_baseline"] = cpu_baseline(w, n_cpu, threads)
     if not args.no_forms:

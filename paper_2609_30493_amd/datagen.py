@@ -38,16 +38,16 @@ class Workload:
 
 
 # The five workloads the measurements are quoted on.
-CFG1 = Workload("frozen-graft n=10k d=32 f32 l2", 10_000, 32, "f32", "l2",
+MIX_10K = Workload("frozen-graft n=10k d=32 f32 l2", 10_000, 32, "f32", "l2",
                 T=4, B=1, ef_h=32, R=24, alpha=1.2, nq=200, data_seed=1,
                 recipe="isotropic")
-CFG2 = Workload("u8 n=1M d=128 l2 T8 B8 ef64 R32", 1_000_000, 128, "u8", "l2",
+SIFT_1M = Workload("u8 n=1M d=128 l2 T8 B8 ef64 R32", 1_000_000, 128, "u8", "l2",
                 T=8, B=8, ef_h=64, R=32, alpha=1.2, nq=10_000, data_seed=2,
                 recipe="clustered_u8")
-CFG3 = Workload("unit f32 n=1183514 d=100 cosine T8 B8 ef128 R64", 1_183_514, 100,
+GLOVE_1183514 = Workload("unit f32 n=1183514 d=100 cosine T8 B8 ef128 R64", 1_183_514, 100,
                 "f32", "cosine", T=8, B=8, ef_h=128, R=64, alpha=1.2, nq=10_000,
                 data_seed=3, recipe="anisotropic_unit")
-CFG4 = Workload("f32 n=1M d=960 l2 T8 B8 ef128 R64", 1_000_000, 960, "f32", "l2",
+GIST_1M = Workload("f32 n=1M d=960 l2 T8 B8 ef128 R64", 1_000_000, 960, "f32", "l2",
                 T=8, B=8, ef_h=128, R=64, alpha=1.2, nq=1_000, data_seed=4,
                 recipe="powerlaw")
 

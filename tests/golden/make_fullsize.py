@@ -10,7 +10,7 @@ Nothing here reads a result of the HIP path.  The GPU tests compare a build
 in the benchmark's launch configuration with these records; they first
 check the input digest, since the generators run on another host there.
 
-Usage: python tests/golden/make_fullsize.py [cfg2,cfg4,cfg3] [--threads N]
+Usage: python tests/golden/make_fullsize.py [sift,gist,glove] [--threads N]
 (an existing record of another workload is kept).  Hours of CPU time.
 """
 from __future__ import annotations
@@ -29,7 +29,7 @@ from oracle import fgo  # noqa: E402
 from paper_2609_30493_amd import datagen as gen  # noqa: E402
 
 OUT = os.path.join(HERE, "fullsize.txt")
-WORKLOADS = {"cfg2": gen.CFG2, "cfg4": gen.CFG4, "cfg3": gen.CFG3}
+WORKLOADS = {"sift": gen.SIFT_1M, "gist": gen.GIST_1M, "glove": gen.GLOVE_1183514}
 COUNTERS = ("scaffold_evals", "harvest_evals", "prune_evals", "finalize_evals", "expansions")
 
 
@@ -83,7 +83,7 @@ def write_records(recs: dict, path: str = OUT) -> None:
     with open(path, "w") as f:
         f.write("# Oracle whole builds at full size (written by tests/golden/make_fullsize.py;\n"
                 "# seeded inputs from paper_2609_30493_amd.datagen, graphs from oracle/ only).\n")
-        for key in ("cfg2", "cfg4", "cfg3"):
+        for key in ("sift", "gist", "glove"):
             if key not in recs:
                 continue
             f.write(f"\n[{key}]\n")
@@ -93,7 +93,7 @@ def write_records(recs: dict, path: str = OUT) -> None:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", nargs="?", default="cfg2,cfg4,cfg3")
+    ap.add_argument("which", nargs="?", default="sift,gist,glove")
     ap.add_argument("--threads", type=int, default=os.cpu_count() or 1)
     args = ap.parse_args()
     recs = read_records()

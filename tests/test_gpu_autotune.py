@@ -18,7 +18,7 @@ def _build_hash(F, data, params, n):
 
 def test_autotune_caches_and_never_changes_the_graph(tmp_path):
     from paper_2609_30493_amd import fgraft as F
-    x = gen.workload_data(gen.CFG2, 60000)
+    x = gen.workload_data(gen.SIFT_1M, 60000)
     n = x.shape[0]
     data = F.make_data(dev(x))
     params = F.make_params(8, 64, 32, 1.2, 8)
@@ -54,11 +54,11 @@ def test_lanes_per_row_never_changes_the_graph(fgo, name):
     graph and counters: the declared order's bits do not depend on it."""
     from paper_2609_30493_amd import fgraft as F
     if name == "u8-d128":
-        x, metric = gen.workload_data(gen.CFG2, 5000), "l2"
+        x, metric = gen.workload_data(gen.SIFT_1M, 5000), "l2"
     elif name == "f32-d64":
         x, metric = gen.isotropic_f32(4000, 64, 16, 0.2, 8), "l2"
     else:
-        x, metric = gen.workload_data(gen.CFG3, 4000), "cosine"
+        x, metric = gen.workload_data(gen.GLOVE_1183514, 4000), "cosine"
     n = x.shape[0]
     T, ef, R, B = 8, 64, 32, 4
     want = fgo.build_graph(fgo.Data(x, metric=metric), 42, fgo.params(T, ef, R, 1.2, B, 0, 8))
@@ -79,7 +79,7 @@ def test_autotune_picks_lanes_and_batched_autotune_keeps_graphs():
     FG_BATCH_AUTOTUNE gives every instance its own build's graph and the
     plain batched counters (the timing launches are not counted)."""
     from paper_2609_30493_amd import fgraft as F
-    x = gen.workload_data(gen.CFG3, 30000)
+    x = gen.workload_data(gen.GLOVE_1183514, 30000)
     data = F.make_data(dev(x), "cosine")
     params = F.make_params(8, 128, 64, 1.2, 8)
     ws = F.alloc_workspace(data, params)

@@ -33,9 +33,9 @@ def _counts_after_expansions(off, ids, roots, E, k):
 def test_visit_log_matches_oracle_sequence(fgo, name):
     from paper_2609_30493_amd import fgraft as F
     if name == "cos-d100-2500":
-        x, metric, T, ef, R, B = gen.workload_data(gen.CFG3, 2500), "cosine", 8, 128, 64, 4
+        x, metric, T, ef, R, B = gen.workload_data(gen.GLOVE_1183514, 2500), "cosine", 8, 128, 64, 4
     else:
-        x, metric, T, ef, R, B = gen.workload_data(gen.CFG2, 4000), "l2", 8, 64, 32, 4
+        x, metric, T, ef, R, B = gen.workload_data(gen.SIFT_1M, 4000), "l2", 8, 64, 32, 4
     n = x.shape[0]
     say(f"visit log parity {name} T={T} ef={ef} R={R} B={B}")
     D = fgo.Data(x, metric=metric)
@@ -76,7 +76,7 @@ def test_visit_log_matches_oracle_sequence(fgo, name):
 
 def test_visit_log_rejects_screened_builds_and_bad_logs():
     from paper_2609_30493_amd import fgraft as F
-    x = gen.workload_data(gen.CFG3, 500)
+    x = gen.workload_data(gen.GLOVE_1183514, 500)
     data = F.make_data(dev(x), "cosine")
     params = F.make_params(4, 32, 16, 1.2, 2, screen=F.SCREEN_BF16)
     ws = F.alloc_workspace(data, params)

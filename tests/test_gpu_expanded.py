@@ -91,9 +91,9 @@ def test_harvest_table_sizes_match_oracle(fgo, table):
     (ef_h = 64, one 16-byte chunk per lane)."""
     from paper_2609_30493_amd import fgraft as F
     T, ef, R, B, b = 8, 64, 32, 8, 5
-    x = gen.workload_data(gen.CFG2, 6000)
+    x = gen.workload_data(gen.SIFT_1M, 6000)
     n = x.shape[0]
-    say(f"harvest parity u8 cfg2-shape n={n} table={table}")
+    say(f"harvest parity u8 sift-shape n={n} table={table}")
     D = fgo.Data(x)
     r, parents, off, ids, _ = fgo.scaffold(D, 42, T)
     P = fgo.params(T, ef, R, 1.2, B, 0, 8)
@@ -113,7 +113,7 @@ def test_harvest_table_sizes_match_oracle(fgo, table):
         assert cg["spilled_queries"] > 0  # the visited table overflowed into the bitset
 
 
-@pytest.mark.parametrize("name,table", [("u8-cfg2-9000", 1024), ("u8-cfg2-9000", 512),
+@pytest.mark.parametrize("name,table", [("u8-sift-9000", 1024), ("u8-sift-9000", 512),
                                         ("f32-cos-d100-3000", 512), ("f32-cos-d100-3000", 1024),
                                         ("f32-cos-d100-3000", 2048), ("f32-cos-d100-3000", 4096),
                                         ("f32-d960-1500", 512)])
@@ -123,12 +123,12 @@ def test_build_table_sizes_match_oracle(fgo, name, table):
     ef_h=128, R=64) at every size, and the GIST-shaped rows (d = 960, the
     matrix-core prune) at 512 (expanded sets beyond 256 go to the device)."""
     from paper_2609_30493_amd import fgraft as F
-    if name == "u8-cfg2-9000":
-        x, metric, T, ef, R, B = gen.workload_data(gen.CFG2, 9000), "l2", 8, 64, 32, 8
+    if name == "u8-sift-9000":
+        x, metric, T, ef, R, B = gen.workload_data(gen.SIFT_1M, 9000), "l2", 8, 64, 32, 8
     elif name == "f32-d960-1500":
-        x, metric, T, ef, R, B = gen.workload_data(gen.CFG4, 1500), "l2", 8, 128, 64, 8
+        x, metric, T, ef, R, B = gen.workload_data(gen.GIST_1M, 1500), "l2", 8, 128, 64, 8
     else:
-        x, metric, T, ef, R, B = gen.workload_data(gen.CFG3, 3000), "cosine", 8, 128, 64, 8
+        x, metric, T, ef, R, B = gen.workload_data(gen.GLOVE_1183514, 3000), "cosine", 8, 128, 64, 8
     n = x.shape[0]
     say(f"build parity {name} table={table}")
     want = fgo.build_graph(fgo.Data(x, metric=metric), 42, fgo.params(T, ef, R, 1.2, B, 0, 8))

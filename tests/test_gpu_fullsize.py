@@ -24,8 +24,8 @@ pytestmark = pytest.mark.gpu
 SAMPLE = 300
 # workload, n, visited-table slots (0: the library's default, as bench.py),
 # key of the oracle's record
-CASES = {"sift-1M": (gen.CFG2, 1_000_000, 0, "cfg2"), "glove-1183514": (gen.CFG3, 1_183_514, 0, "cfg3"),
-         "gist-1M": (gen.CFG4, 1_000_000, 0, "cfg4")}
+CASES = {"sift-1M": (gen.SIFT_1M, 1_000_000, 0, "sift"), "glove-1183514": (gen.GLOVE_1183514, 1_183_514, 0, "glove"),
+         "gist-1M": (gen.GIST_1M, 1_000_000, 0, "gist")}
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize.txt")
 
 

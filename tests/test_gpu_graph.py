@@ -18,8 +18,8 @@ def _lib():
 DATASETS = {
     "u8-d16-3000": lambda: (gen.small_u8(3000, 16, 3, hi=256), "l2"),
     "u8-ties-2000": lambda: (gen.small_u8(2000, 32, 5, hi=3), "l2"),
-    "u8-cfg2-9000": lambda: (gen.workload_data(gen.CFG2, 9000), "l2"),
-    "f32-d32-2500": lambda: (gen.workload_data(gen.CFG1, 2500), "l2"),
+    "u8-sift-9000": lambda: (gen.workload_data(gen.SIFT_1M, 9000), "l2"),
+    "f32-d32-2500": lambda: (gen.workload_data(gen.MIX_10K, 2500), "l2"),
     "f32-cos-d100-1500": lambda: (gen.anisotropic_unit_f32(1500, 100, 20, 3), "cosine"),
     "f32-d960-600": lambda: (gen.powerlaw_f32(600, 960, 10, 4), "l2"),
     "collinear-400": lambda: (gen.degenerate_f32("collinear", 400, 4, 5), "l2"),
@@ -36,7 +36,7 @@ DATASETS = {
     # the longest rows each kind takes, and a set for every parameter at its bound
     "f32-d1024-400": lambda: (gen.powerlaw_f32(400, 1024, 8, 7), "l2"),
     "u8-d256-1500": lambda: (gen.small_u8(1500, 256, 8, hi=256), "l2"),
-    "f32-d32-600": lambda: (gen.workload_data(gen.CFG1, 600), "l2"),
+    "f32-d32-600": lambda: (gen.workload_data(gen.MIX_10K, 600), "l2"),
 }
 
 
@@ -46,7 +46,7 @@ def _data(name):
     return np.ascontiguousarray(x), metric
 
 
-@pytest.mark.parametrize("name,T", [("u8-d16-3000", 4), ("u8-ties-2000", 3), ("u8-cfg2-9000", 8),
+@pytest.mark.parametrize("name,T", [("u8-d16-3000", 4), ("u8-ties-2000", 3), ("u8-sift-9000", 8),
                                     ("f32-d32-2500", 4), ("f32-cos-d100-1500", 8),
                                     ("f32-d960-600", 2), ("collinear-400", 3),
                                     ("duplicates-900", 4), ("identical-50", 2), ("pair-2", 2),
@@ -74,7 +74,7 @@ def test_scaffold_matches_oracle(fgo, name, T):
 
 
 @pytest.mark.parametrize("name,T,R,B,b", [("u8-d16-3000", 4, 16, 4, 2), ("f32-d32-2500", 4, 24, 3, 0),
-                                          ("u8-cfg2-9000", 8, 32, 8, 6), ("hub-u8-6000", 4, 16, 2, 0),
+                                          ("u8-sift-9000", 8, 32, 8, 6), ("hub-u8-6000", 4, 16, 2, 0),
                                           ("hub-f32-6000", 4, 16, 2, 1)])
 def test_merge_matches_oracle(fgo, name, T, R, B, b):
     F = _lib()
@@ -140,7 +140,7 @@ def test_finalize_matches_oracle(fgo, name, T, R, B, reprune):
 
 BUILDS = [
     # name, T, ef, R, alpha, B
-    ("u8-cfg2-9000", 8, 64, 32, 1.2, 8),
+    ("u8-sift-9000", 8, 64, 32, 1.2, 8),
     ("f32-d32-2500", 4, 32, 24, 1.2, 1),
     ("f32-cos-d100-1500", 8, 128, 64, 1.2, 4),
     ("u8-ties-2000", 3, 16, 10, 1.0, 0),
@@ -208,7 +208,7 @@ def test_build_graph_repeatable_and_b0_equals_b1(fgo):
 def test_search_matches_oracle(fgo, L):
     F = _lib()
     say(f"search parity L={L}")
-    w = gen.CFG1
+    w = gen.MIX_10K
     x = gen.workload_data(w, 4000)
     q = gen.workload_queries(w, 150)
     D = fgo.Data(x)
@@ -229,11 +229,11 @@ def test_search_matches_oracle(fgo, L):
     assert np.array_equal(host_u32(oe), ev_o)
 
 
-def test_u8_search_distances_and_recall_cfg1_gpu_graph(fgo):
+def test_u8_search_distances_and_recall_mix10k_gpu_graph(fgo):
     """The GPU-built frozen-Graft graph reaches recall@10 >= 0.95."""
     import checkers as ck
     F = _lib()
-    w = gen.CFG1
+    w = gen.MIX_10K
     x = gen.workload_data(w)
     q = gen.workload_queries(w)
     data, params, ws, G, arrs, c, t = _gpu_build(F, x, "l2", w.T, w.ef_h, w.R, w.alpha, w.B)

@@ -15,10 +15,10 @@ def _case(name):
         return gen.small_u8(3000, 16, 3, hi=256), "l2"
     if name == "u8-d128-ties":
         return gen.small_u8(2500, 128, 4, hi=3), "l2"
-    if name == "u8-cfg2-shape":
-        return gen.workload_data(gen.CFG2, 6000), "l2"
+    if name == "u8-sift-shape":
+        return gen.workload_data(gen.SIFT_1M, 6000), "l2"
     if name == "f32-d32":
-        return gen.workload_data(gen.CFG1, 4000), "l2"
+        return gen.workload_data(gen.MIX_10K, 4000), "l2"
     if name == "f32-d100-cos":
         return gen.anisotropic_unit_f32(2500, 100, 20, 3), "cosine"
     if name == "f32-d960":
@@ -32,7 +32,7 @@ CASES = [
     # name, T, ef, R, alpha, B, b
     ("u8-d16", 3, 32, 16, 1.2, 3, 1),
     ("u8-d128-ties", 4, 24, 12, 1.0, 2, 0),
-    ("u8-cfg2-shape", 8, 64, 32, 1.2, 8, 5),
+    ("u8-sift-shape", 8, 64, 32, 1.2, 8, 5),
     ("f32-d32", 4, 32, 24, 1.2, 1, 0),
     ("f32-d100-cos", 8, 128, 64, 1.2, 4, 3),
     ("f32-d960", 8, 64, 32, 1.2, 2, 1),

@@ -407,10 +407,10 @@ def test_search_full_width_is_exact_knn(fgo):
     assert np.all(ev == 150)
 
 
-def test_recall_cfg1_frozen_graft(fgo):
+def test_recall_mix10k_frozen_graft(fgo):
     """The frozen-Graft workload (n = 10k, d = 32, T = 4, ef_h = 32, R = 24)
     reaches tie-aware recall@10 >= 0.95 against float64 brute force."""
-    w = gen.CFG1
+    w = gen.MIX_10K
     x = gen.workload_data(w)
     q = gen.workload_queries(w)
     D = fgo.Data(x)
@@ -437,7 +437,7 @@ def test_fp32_graph_close_to_fp64_graph(fgo):
     tie; 100% measured), and every edge's float32 distance is within the
     declared order's relative error bound (d/16 + 6) 2^-24 of the float64
     one; the maximum and mean relative errors are printed."""
-    w = gen.CFG1
+    w = gen.MIX_10K
     n = 3000
     x = gen.workload_data(w, n)
     P = fgo.params(w.T, w.ef_h, w.R, w.alpha, 2, 0, 8)

@@ -47,8 +47,8 @@ def _both(data, G, ws, q, k, L, dtype):
 def test_noalloc_search_equals_search_twice_then_smaller():
     assert F.search_noalloc_scratch_bytes() == 64 << 20
     cases = [
-        ("first: float32 cosine n=24000 d=100, 400 queries, L=96", gen.CFG3, 24_000, 400, 96),
-        ("second: uint8 n=6000 d=128, 150 queries, L=64", gen.CFG2, 6_000, 150, 64),
+        ("first: float32 cosine n=24000 d=100, 400 queries, L=96", gen.GLOVE_1183514, 24_000, 400, 96),
+        ("second: uint8 n=6000 d=128, 150 queries, L=64", gen.SIFT_1M, 6_000, 150, 64),
     ]
     for label, w, n, nq, L in cases:
         say(f"[noalloc] {label}")
