@@ -55,3 +55,19 @@ def test_roots_without_gpu():
     assert rc == 0
     assert len(set(roots)) == 4 and all(r < 1000 for r in roots)
     assert lib.fg_roots(ctypes.c_uint64(0), ctypes.c_int64(3), ctypes.c_uint32(4), roots) == -1
+
+
+def test_screen_row_bytes_without_gpu():
+    """fg_screen_row_bytes is host-only: narrow rows are whole 128-byte
+    lines holding the codes (bfloat16: 2d rounded up to 32; fp8: d rounded
+    up to 16) and the 16-byte trailer, with less than a line to spare; bad
+    kinds and sizes give 0."""
+    lib = ctypes.CDLL(LIB)
+    lib.fg_screen_row_bytes.restype = ctypes.c_int64
+    lib.fg_screen_row_bytes.argtypes = [ctypes.c_int32, ctypes.c_uint32]
+    for d in (68, 96, 100, 128, 256, 260, 512, 960, 1024):
+        for kind, codes in ((1, (2 * d + 31) // 32 * 32), (2, (d + 15) // 16 * 16)):
+            rb = lib.fg_screen_row_bytes(d, kind)
+            assert rb % 128 == 0 and codes + 16 <= rb < codes + 16 + 128, (d, kind, rb)
+    assert lib.fg_screen_row_bytes(100, 1) == 256 and lib.fg_screen_row_bytes(100, 2) == 128
+    assert lib.fg_screen_row_bytes(0, 1) == 0 and lib.fg_screen_row_bytes(100, 7) == 0
