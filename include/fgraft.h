@@ -97,9 +97,12 @@ typedef struct {
  * of each harvest search's on-chip visited table, 512, 1024, 2048 or 4096
  * (0 = 4096 for FG_F32 rows of more than 256 elements or ef_h > 128, else
  * 1024 for rows of at most 16 bytes per lane -- uint8 d <= 256 or FG_F32
- * d <= 64 -- and 2048 for the rest; ef_h > 128 always uses 4096; 512 and
- * 1024 apply to the unscreened harvest with ef_h <= 128 and the library's
- * lanes per row, else 2048 is used).  Smaller tables let more searches run
+ * d <= 64 -- and for the screened harvest (FG_SCREEN_BF16 or _FP8E4M3) of
+ * rows of at most 256 elements, and 2048 for the rest; ef_h > 128 always
+ * uses 4096; 512 and 1024 apply to the unscreened harvest with ef_h <= 128
+ * and the library's lanes per row, and 1024 (also for a 512 request) to
+ * the screened harvest with ef_h <= 128 of rows of at most 256 elements;
+ * otherwise 2048 is used).  Smaller tables let more searches run
  * per compute unit; a search whose visits outgrow its table continues in a
  * device bitset.  A search's
  * expanded set is sorted and pruned on chip up to half the table's slots and

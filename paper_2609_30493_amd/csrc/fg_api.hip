@@ -106,11 +106,16 @@ uint32_t b_eff(const fg_params* p) { return p->B > 1 ? p->B : 1; }
 // 4096: their registers already hold residency at two searches per SIMD and
 // the larger table keeps searches off the device bitset (the 10^6 x 960
 // harvest: 1.88 s, against 1.98 at 2048); ef_h > 128 takes 4096.
+// The screened forms' kernels for rows of 2..4 chunks per lane take 1024
+// (the 1,183,514 x 100 cosine harvest with the fp8 screen: 2.69 s against
+// 2.86 at 2048; at three searches per SIMD the smaller table lets a twelfth
+// search per compute unit fit, and the screen's rounds are latency-bound).
 int table_request(const fg_params* p, int nch = 1) {
   if (p->beam_table_slots == 512 || p->beam_table_slots == 1024 || p->beam_table_slots == 2048 ||
       p->beam_table_slots == 4096)
     return (int)p->beam_table_slots;
   if (nch >= 16 || p->ef_h > 128) return 4096;
+  if (search_screen(p->screen) != SCR_NONE) return nch <= 4 ? 1024 : 2048;
   return nch == 1 ? 1024 : 2048;
 }
 
@@ -269,9 +274,15 @@ fg_status harvest_launch(const Shape& s, const uint64_t* off, const uint32_t* id
   const int lanes = screen == SCR_NONE ? (int)P->lanes_per_row : 0;
   const int nch = beam_chunks_per_lane(s, lanes);
   int hslots = log ? 4096 : beam_table_slots(ef, false, table_request(P, nch), nch);
-  // the small tables exist for the plain kernels of the library's shape
+  // the small tables exist for the plain kernels of the library's shape;
+  // the screened kernels have 1024 for rows of up to 4 chunks per lane
   int Lv = 0, nv = 0;
-  if (hslots < 2048 && (screen != SCR_NONE || lanes_variant(s.dk, s.Q, lanes, &Lv, &nv))) hslots = 2048;
+  if (screen != SCR_NONE && screen != kBeamLog) {
+    if (hslots < 1024) hslots = 1024;
+    if (hslots == 1024 && nch > 4) hslots = 2048;
+  } else if (hslots < 2048 && lanes_variant(s.dk, s.Q, lanes, &Lv, &nv)) {
+    hslots = 2048;
+  }
   int grid = beam_grid(s, ef, false, hslots, screen, (int)P->waves_per_cu, lanes);
   if (grid <= 0) return set_error("no beam kernel for this row size / ef_h"), FG_EUNSUPPORTED;
   BeamArgs a{};
@@ -1069,6 +1080,7 @@ fg_status tune_harvest(const Shape& s, const uint64_t* off, const uint32_t* ids,
     const int nch = beam_chunks_per_lane(s, (int)ln);
     std::vector<unsigned> tables;
     if (ef <= 128 && ln == 0 && Q.screen == FG_SCREEN_NONE) tables = {512, 1024, 2048, 4096};
+    else if (ef <= 128 && search_screen(Q.screen) != SCR_NONE && nch <= 4) tables = {1024, 2048, 4096};
     else if (ef <= 128) tables = {2048, 4096};
     else tables = {4096};
     for (unsigned tb : tables) {

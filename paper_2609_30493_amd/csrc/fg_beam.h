@@ -526,11 +526,12 @@ __device__ int prune_wave(const RowSet& X, float alpha, int R, const uint64_t* s
 // Waves per SIMD the register budget aims at: more searches in flight hide
 // more gather latency.  Four for rows of one or two chunks per lane with a
 // table of at most 1024 slots (at most about 10 KB of LDS per wave), three
-// for such rows with larger tables, two for the longest rows, else whatever
-// the registers allow.
-template <int NCH, int HS>
+// for such rows with larger tables and for the screened kernels of such
+// rows (whose screen needs more than the 128 registers of four), two for
+// the longest rows, else whatever the registers allow.
+template <int NCH, int HS, int SCR = 0>
 constexpr int beam_waves_per_eu() {
-  return (NCH <= 2 && HS <= 1024) ? 4 : (NCH <= 2 ? 3 : (NCH >= 16 ? 2 : 1));
+  return (NCH <= 2 && HS <= 1024 && SCR == 0) ? 4 : (NCH <= 2 ? 3 : (NCH >= 16 ? 2 : 1));
 }
 
 // ------------------------------------------------------------ Gram-tile prune
@@ -894,7 +895,7 @@ __device__ int prune_gram(const RowSet& X, int d, const GramSplit& split, const 
 }
 
 template <int DK, int L, int NCH, int EFMAX, int HSLOTS, bool SEARCH, int SCR = SCR_NONE, bool LOG = false>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(beam_waves_per_eu<NCH, HSLOTS>())))
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(beam_waves_per_eu<NCH, HSLOTS, SCR>())))
 k_beam(BeamArgs A) {
   __shared__ WaveLDS<EFMAX, HSLOTS> S;
   const int lane = lane_id();

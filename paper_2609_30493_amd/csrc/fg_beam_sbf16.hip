@@ -8,8 +8,11 @@ namespace {
 
 template <int DK, int NCH, int EFMAX>
 void* kp(int hslots) {
-  if constexpr (EFMAX <= 128)
+  if constexpr (EFMAX <= 128) {
     if (hslots == 2048) return reinterpret_cast<void*>(&k_beam<DK, 16, NCH, EFMAX, 2048, false, SCR_BF16>);
+    if constexpr (NCH <= 4)
+      if (hslots == 1024) return reinterpret_cast<void*>(&k_beam<DK, 16, NCH, EFMAX, 1024, false, SCR_BF16>);
+  }
   return reinterpret_cast<void*>(&k_beam<DK, 16, NCH, EFMAX, 4096, false, SCR_BF16>);
 }
 

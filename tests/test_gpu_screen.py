@@ -139,10 +139,10 @@ SCREEN_BUILDS = [
 ]
 
 
-def _build(F, x, metric, T, ef, R, B, screen):
+def _build(F, x, metric, T, ef, R, B, screen, table=0):
     n = x.shape[0]
     data = F.make_data(dev(x), metric)
-    params = F.make_params(T, ef, R, 1.2, B, screen=screen)
+    params = F.make_params(T, ef, R, 1.2, B, screen=screen, beam_table_slots=table)
     ws = F.alloc_workspace(data, params)
     gn, gcnt, sp, rt = empty_u32(n, R), empty_u32(n, fill=0), empty_u32(n), empty_u32(T)
     G = F.make_graph(gn, gcnt, sp, rt, T)
@@ -168,6 +168,25 @@ def test_screened_builds_equal_unscreened_and_oracle(fgo, case):
             assert k[key] == k0[key], key
         assert 0 < k["screen_rejected"] < k["harvest_evals"]
         assert k0["screen_rejected"] == 0
+
+
+@pytest.mark.parametrize("table", [512, 1024, 2048, 4096])
+def test_screened_builds_at_every_table_size(table):
+    """The screened kernels' tables (1024 for rows of up to 4 chunks per lane
+    by default, a 512 request served by 1024, 2048 and 4096 on request):
+    the same graph and counters as the unscreened build, which the test
+    above ties to the oracle."""
+    F = _lib()
+    for name, mk, metric, T, ef, R, B in (SCREEN_BUILDS[0], SCREEN_BUILDS[1], SCREEN_BUILDS[3]):
+        x = np.ascontiguousarray(mk().astype(np.float32))
+        say(f"screened build {name} table={table}")
+        h0, g0, c0, k0 = _build(F, x, metric, T, ef, R, B, F.SCREEN_NONE)
+        for scr in (F.SCREEN_BF16, F.SCREEN_FP8E4M3):
+            h, g, c, k = _build(F, x, metric, T, ef, R, B, scr, table)
+            assert h == h0 and np.array_equal(g, g0) and np.array_equal(c, c0), (name, scr)
+            for key in ("harvest_evals", "expansions", "prune_evals", "finalize_evals", "scaffold_evals"):
+                assert k[key] == k0[key], (name, scr, key)
+            assert k["screen_rejected"] > 0
 
 
 def test_screened_harvest_block_equals_unscreened(fgo):
