@@ -578,7 +578,7 @@ def screen_compare(args):
         xd = torch.from_numpy(x).cuda()
         metric = "cosine" if w.metric == "cosine" else "l2"
         data = F.make_data(xd, metric)
-        forms = (F.SCREEN_NONE, F.SCREEN_BF16, F.SCREEN_FP8E4M3)
+        forms = (F.SCREEN_NONE, F.SCREEN_BF16, F.SCREEN_FP8E4M3, F.SCREEN_INT8)
         if w.d > 256:
             forms += (F.SCREEN_BF16_PRUNE,)
         if args.forms:
@@ -614,7 +614,7 @@ def screen_compare(args):
         base_h = np.array([r["harvest_ms"] for r in res[0]])
         base_b = np.array([r["build_s"] for r in res[0]])
         row_bytes = 4 * w.d
-        form_names = {0: "fp32", 1: "bf16", 2: "fp8e4m3", 3: "bf16split_prune"}
+        form_names = {0: "fp32", 1: "bf16", 2: "fp8e4m3", 3: "bf16split_prune", 4: "int8"}
         for f, name in ((f, form_names[f]) for f in forms):
             h = np.array([r["harvest_ms"] for r in res[f]])
             b = np.array([r["build_s"] for r in res[f]])
@@ -622,7 +622,8 @@ def screen_compare(args):
             rej = res[f][0]["rejected"]
             # a screened evaluation reads the narrow row's codes and its
             # 16-byte trailer (error norm, norm, fp8 factor)
-            narrow = {0: 0, 1: (2 * w.d + 31) // 32 * 32 + 16, 2: (w.d + 15) // 16 * 16 + 16, 3: 0}[f]
+            narrow = {0: 0, 1: (2 * w.d + 31) // 32 * 32 + 16, 2: (w.d + 15) // 16 * 16 + 16, 3: 0,
+                      4: (w.d + 15) // 16 * 16 + 16}[f]
             e = {"harvest_ms_median": float(np.median(h)), "build_s_median": float(np.median(b)),
                  "harvest_evals_per_s": float(ev / (np.median(h) / 1e3)),
                  "screen_rejected_frac": rej / ev,
@@ -984,7 +985,7 @@ def forms_vs_fp32(key, w, st):
     out = {}
     if w.dtype != "f32" or w.d <= 64:
         return out
-    for f, name in ((F.SCREEN_FP8E4M3, "fp8e4m3"), (F.SCREEN_BF16, "bf16")):
+    for f, name in ((F.SCREEN_FP8E4M3, "fp8e4m3"), (F.SCREEN_BF16, "bf16"), (F.SCREEN_INT8, "int8")):
         params = F.make_params(w.T, w.ef_h, w.R, w.alpha, w.B, screen=f)
         ws = F.alloc_workspace(data, params)
         F.build_graph(data, w.build_seed, params, G, ws, timings=True)

@@ -63,8 +63,9 @@ typedef enum { FG_L2SQ = 0, FG_COSINE = 1 } fg_metric;
  * proven error margins; a decision the margin settles is taken from the
  * cheap value, every other one from the exact float32 distance, so graphs,
  * counts and hashes are those of FG_SCREEN_NONE.
- *   search screen (FG_SCREEN_BF16, FG_SCREEN_FP8E4M3): a new candidate that
- *     provably cannot enter the full beam is not evaluated exactly;
+ *   search screen (FG_SCREEN_BF16, FG_SCREEN_FP8E4M3, FG_SCREEN_INT8): a
+ *     new candidate that provably cannot enter the full beam is not
+ *     evaluated exactly;
  *   split prune tiles (FG_SCREEN_BF16, FG_SCREEN_BF16_PRUNE; 256 < d <= 1024):
  *     the occlusion prune's Gram tiles (harvest and finalize) come from a
  *     bfloat16 split x = hi + lo + e, |e| <= 2^-16 |x| elementwise, three
@@ -74,7 +75,10 @@ typedef enum {
   FG_SCREEN_NONE = 0,
   FG_SCREEN_BF16 = 1,       /* bfloat16 copy, round to nearest even: search screen and split prune tiles */
   FG_SCREEN_FP8E4M3 = 2,    /* fp8 e4m3 (OCP) copy with a power-of-two scale per row: search screen */
-  FG_SCREEN_BF16_PRUNE = 3  /* split prune tiles only (256 < d <= 1024) */
+  FG_SCREEN_BF16_PRUNE = 3, /* split prune tiles only (256 < d <= 1024) */
+  FG_SCREEN_INT8 = 4        /* int8 codes of x / s, s = max|x_i| / 127 per row: search screen; for
+                               FG_COSINE the candidate's dot product with the point's own codes is
+                               exact in integers */
 } fg_screen;
 
 /* Row-major data in device memory.  FG_F32 needs d % 4 == 0; FG_U8 needs
@@ -97,7 +101,7 @@ typedef struct {
  * of each harvest search's on-chip visited table, 512, 1024, 2048 or 4096
  * (0 = 4096 for FG_F32 rows of more than 256 elements or ef_h > 128, else
  * 1024 for rows of at most 16 bytes per lane -- uint8 d <= 256 or FG_F32
- * d <= 64 -- and for the screened harvest (FG_SCREEN_BF16 or _FP8E4M3) of
+ * d <= 64 -- and for the screened harvest (FG_SCREEN_BF16, _FP8E4M3, _INT8) of
  * rows of at most 256 elements, and 2048 for the rest; ef_h > 128 always
  * uses 4096; 512 and 1024 apply to the unscreened harvest with ef_h <= 128
  * and the library's lanes per row, and 1024 (also for a 512 request) to
@@ -358,18 +362,20 @@ fg_status fg_leaf_knn(const fg_data* data, uint32_t leaf_size, uint32_t R,
                       void* ws_dev, size_t ws_bytes, void* stream);
 
 /* The narrow copy a screened harvest reads (fg_screen), for inspection:
- * row i of the data as bfloat16 (round to nearest even) or as fp8 e4m3 (OCP)
- * codes of x * 2^k, k the largest integer with max|x_i| * 2^k <= 448, in
+ * row i of the data as bfloat16 (round to nearest even), as fp8 e4m3 (OCP)
+ * codes of x * 2^k, k the largest integer with max|x_i| * 2^k <= 448, or as
+ * int8 codes rint(x / s) clamped to [-127, 127], s = fl(max|x_i| / 127), in
  * the data's element order, rows fg_screen_row_bytes(d, screen) bytes apart
  * (a whole number of 128-byte lines).  A row holds the codes (bfloat16: 2d
- * bytes rounded up to a multiple of 32, pad bytes written as zero; fp8: d
- * rounded up to a multiple of 16, pad bytes not written), then a 16-byte
- * trailer of four floats (err, norm, sinv, 0) equal to the values below,
- * then padding (zero for bfloat16, not written for fp8).
+ * bytes rounded up to a multiple of 32, pad bytes written as zero; fp8 and
+ * int8: d rounded up to a multiple of 16, pad bytes not written), then a
+ * 16-byte trailer of four floats (err, norm, sinv, 0) equal to the values
+ * below, then padding (zero for bfloat16, not written otherwise).
  * err_dev[i] >= |x^_i - x_i| and norm_dev[i] >= |x_i| (float32 sums of
- * scaled squares raised by their rounding bound), sinv_dev[i] = 2^-k (1 for
- * bfloat16), where x^_i is the copy read back (fp8: code * 2^-k).  FG_F32
- * data with d > 64 only.  Asynchronous on `stream`. */
+ * scaled squares raised by their rounding bound), sinv_dev[i] = 2^-k (fp8),
+ * s (int8), 1 (bfloat16), where x^_i is the copy read back (fp8: code * 2^-k;
+ * int8: fl(code * s), each element's product rounded once).  FG_F32 data
+ * with d > 64 only.  Asynchronous on `stream`. */
 int64_t fg_screen_row_bytes(int32_t d, uint32_t screen);
 fg_status fg_screen_copy(const fg_data* data, uint32_t screen, void* xs_dev,
                          float* err_dev, float* norm_dev, float* sinv_dev,

@@ -66,7 +66,7 @@ bool check_params(const fg_params* p, int64_t n, bool need_ef = true) {
   if (p->beam_table_slots != 0 && p->beam_table_slots != 512 && p->beam_table_slots != 1024 &&
       p->beam_table_slots != 2048 && p->beam_table_slots != 4096)
     return set_error("beam_table_slots must be 0, 512, 1024, 2048 or 4096"), false;
-  if (p->screen > FG_SCREEN_BF16_PRUNE) return set_error("screen must be an fg_screen"), false;
+  if (p->screen > FG_SCREEN_INT8) return set_error("screen must be an fg_screen"), false;
   if (p->waves_per_cu > 64) return set_error("waves_per_cu must be 0..64"), false;
   if (p->lanes_per_row != 0 && p->lanes_per_row != 4 && p->lanes_per_row != 8 && p->lanes_per_row != 16)
     return set_error("lanes_per_row must be 0, 4, 8 or 16"), false;
@@ -86,13 +86,18 @@ bool check_screen(const fg_params* p, const Shape& s) {
 
 // The narrow copy's kind, and whether the prune's Gram tiles come from the
 // bfloat16 split (float32 rows of 257..1024 elements).
-int copy_kind(uint32_t screen) { return screen == FG_SCREEN_FP8E4M3 ? SCR_FP8 : SCR_BF16; }
+int copy_kind(uint32_t screen) {
+  return screen == FG_SCREEN_FP8E4M3 ? SCR_FP8 : screen == FG_SCREEN_INT8 ? SCR_INT8 : SCR_BF16;
+}
 bool split_tiles(uint32_t screen, int d) {
   return (screen == FG_SCREEN_BF16 || screen == FG_SCREEN_BF16_PRUNE) && d > 256 && d <= 1024 && d % 4 == 0;
 }
 // The search-side screen's kernel variant (none for FG_SCREEN_BF16_PRUNE).
 int search_screen(uint32_t screen) {
-  return screen == FG_SCREEN_BF16 ? SCR_BF16 : screen == FG_SCREEN_FP8E4M3 ? SCR_FP8 : SCR_NONE;
+  return screen == FG_SCREEN_BF16 ? SCR_BF16
+         : screen == FG_SCREEN_FP8E4M3 ? SCR_FP8
+         : screen == FG_SCREEN_INT8 ? SCR_INT8
+                                    : SCR_NONE;
 }
 
 uint32_t b_eff(const fg_params* p) { return p->B > 1 ? p->B : 1; }
@@ -621,22 +626,22 @@ fg_status fg_leaf_knn(const fg_data* data, uint32_t leaf_size, uint32_t R, int u
 }
 
 int64_t fg_screen_row_bytes(int32_t d, uint32_t screen) {
-  if (d < 1 || (screen != FG_SCREEN_BF16 && screen != FG_SCREEN_FP8E4M3)) return 0;
-  return screen_stride(d, (int)screen);
+  if (d < 1 || (screen != FG_SCREEN_BF16 && screen != FG_SCREEN_FP8E4M3 && screen != FG_SCREEN_INT8)) return 0;
+  return screen_stride(d, copy_kind(screen));
 }
 
 fg_status fg_screen_copy(const fg_data* data, uint32_t screen, void* xs_dev, float* err_dev, float* norm_dev,
                          float* sinv_dev, void* stream) {
   Shape s;
   if (!make_shape(data, &s)) return FG_EINVAL;
-  if (screen != FG_SCREEN_BF16 && screen != FG_SCREEN_FP8E4M3)
-    return set_error("screen must be FG_SCREEN_BF16 or FG_SCREEN_FP8E4M3"), FG_EINVAL;
+  if (screen != FG_SCREEN_BF16 && screen != FG_SCREEN_FP8E4M3 && screen != FG_SCREEN_INT8)
+    return set_error("screen must be FG_SCREEN_BF16, FG_SCREEN_FP8E4M3 or FG_SCREEN_INT8"), FG_EINVAL;
   fg_params P{};
   P.screen = screen;
   if (!check_screen(&P, s)) return FG_EUNSUPPORTED;
   if (!xs_dev || !err_dev || !norm_dev || !sinv_dev) return set_error("NULL output"), FG_EINVAL;
   if (reinterpret_cast<uintptr_t>(xs_dev) % 16) return set_error("xs_dev must be 16-byte aligned"), FG_EINVAL;
-  FG_HIP(make_screen(s, (int)screen, static_cast<uint8_t*>(xs_dev), err_dev, norm_dev, sinv_dev,
+  FG_HIP(make_screen(s, copy_kind(screen), static_cast<uint8_t*>(xs_dev), err_dev, norm_dev, sinv_dev,
                      static_cast<hipStream_t>(stream)));
   return FG_OK;
 }

@@ -169,7 +169,7 @@ constexpr int kGramMax = 1024;   // candidates the Gram-tile prune takes
 constexpr int kGramPF16 = 4;     // split-tile steps in flight
 constexpr int kGramSlots = 2048; // wave slots that have Gram scratch
 
-enum ScreenKind { SCR_NONE = 0, SCR_BF16 = 1, SCR_FP8 = 2 };
+enum ScreenKind { SCR_NONE = 0, SCR_BF16 = 1, SCR_FP8 = 2, SCR_INT8 = 3 };
 
 // One narrow row's codes as lane g of a group holds them: chunk q = g + L*i
 // (four elements) as two words of bfloat16 or one word of fp8, zero past Q.
@@ -215,6 +215,10 @@ __device__ __forceinline__ float group_screen(const Chunks<L, NCH>& a, const Nar
         const uint32_t w0 = r.w[2 * i], w1 = r.w[2 * i + 1];
         xb = make_float4(__uint_as_float(w0 << 16), __uint_as_float(w0 & 0xFFFF0000u), __uint_as_float(w1 << 16),
                          __uint_as_float(w1 & 0xFFFF0000u));
+      } else if constexpr (SCR == SCR_INT8) {  // squared L2: each code read back as fl(code * s)
+        const int w = (int)r.w[i];
+        xb = make_float4((float)((w << 24) >> 24) * sinv, (float)((w << 16) >> 24) * sinv,
+                         (float)((w << 8) >> 24) * sinv, (float)(w >> 24) * sinv);
       } else {
         const int w = (int)r.w[i];
         const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8(w, false);
@@ -240,6 +244,20 @@ __device__ __forceinline__ float group_screen(const Chunks<L, NCH>& a, const Nar
   }
 #pragma unroll
   for (int off = L / 2; off >= 1; off >>= 1) acc = acc + __shfl_xor(acc, off, 64);
+  return acc;
+}
+
+// int8 codes of the point and of a candidate row, dot product over the
+// group in exact integer arithmetic (|sum| <= 127^2 d < 2^24, so the result
+// converts to float exactly).
+template <int L, int NCH>
+__device__ __forceinline__ int group_dot_i8(const NarrowChunks<NCH, SCR_INT8>& p,
+                                            const NarrowChunks<NCH, SCR_INT8>& r) {
+  int acc = 0;
+#pragma unroll
+  for (int i = 0; i < NCH; i++) acc = __builtin_amdgcn_sdot4((int)p.w[i], (int)r.w[i], acc, false);
+#pragma unroll
+  for (int off = L / 2; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
   return acc;
 }
 
@@ -278,6 +296,23 @@ __device__ __forceinline__ float screen_eps(float dt, ScreenGammas k, float E, f
   return 2.0f * eps;
 }
 
+// The same for cosine over int8 codes of both rows: dt = 1 - fl(fl(s_p s_u) I)
+// with I the exact integer dot product, so <p^,u^> = s_p s_u I with p^, u^
+// the codes times their scales in exact arithmetic.  Their distances from p
+// and u are at most E' = E + u (|x| + E) (E bounds the distance from the
+// copy read back with one rounding per element):
+//   |<p,u> - <p^,u^>| <= E'_p |u| + |p^| E'_u, |p^| <= |p| + E'_p = P,
+//   |u^| <= U; the two products round by at most 2.0001 u P U, 1 - x by
+//   u (1 + P U); the declared order's sum errs by gc |p||u| and its 1 - s
+//   by u (1 + |p||u|).  Doubled as above.
+__device__ __forceinline__ float screen_eps_i8(ScreenGammas k, float Ep, float np, float Eu, float nu) {
+  const float u = 5.9604645e-08f;  // 2^-24
+  const float Epp = Ep + u * (np + Ep), Eup = Eu + u * (nu + Eu);
+  const float P = np + Epp, U = nu + Eup;
+  const float eps = Epp * nu + P * Eup + (k.gc + 4.0f * u) * P * U + 4.0f * u * (1.0f + P * U);
+  return 2.0f * eps;
+}
+
 // Screen the cnt new ids in ids_lds (cnt <= 256) against the beam's worst
 // exact distance w: ids that cannot enter the beam are dropped, the others
 // are compacted to the front of ids_lds (in an order of their own: the
@@ -293,7 +328,9 @@ __device__ __forceinline__ float screen_eps(float dt, ScreenGammas k, float E, f
 // survivors.
 template <int DK, int L, int NCH, int SCR>
 __device__ __forceinline__ int screen_filter(const BeamArgs& A, const Chunks<L, NCH>& a, float np,
+                                             const NarrowChunks<NCH, SCR>& pc, float p_err, float p_scale,
                                              uint32_t* ids_lds, int cnt, float w) {
+  constexpr bool kIntDot = SCR == SCR_INT8 && DK == F32COS;  // the point's own codes against the row's
   constexpr int G = 64 / L;
   constexpr int RB = (NCH >= 16) ? 1 : 32 / NCH;
   static_assert(RB <= L, "a lane owns at most one row of a round");
@@ -320,17 +357,27 @@ __device__ __forceinline__ int screen_filter(const BeamArgs& A, const Chunks<L, 
     for (int t = 0; t < RB; t++) load_narrow<L, NCH, SCR>(rc[t], A.xs + (size_t)u[t] * A.xs_stride, A.Q, g);
 #pragma unroll
     for (int t = 0; t < RB; t++) {
-      // squared L2 over fp8 codes scales each element by its row's factor,
-      // which lane t of the group loaded
-      const float sinv = (SCR == SCR_FP8 && DK == F32L2) ? __shfl(tr.z, base + t, 64) : 1.0f;
-      dt[t] = group_screen<DK, L, NCH, SCR>(a, rc[t], sinv, A.Q, g);
+      if constexpr (kIntDot) {
+        dt[t] = (float)group_dot_i8<L, NCH>(pc, rc[t]);
+      } else {
+        // squared L2 over fp8 or int8 codes scales each element by its
+        // row's factor, which lane t of the group loaded
+        const float sinv = ((SCR == SCR_FP8 || SCR == SCR_INT8) && DK == F32L2) ? __shfl(tr.z, base + t, 64) : 1.0f;
+        dt[t] = group_screen<DK, L, NCH, SCR>(a, rc[t], sinv, A.Q, g);
+      }
     }
     float own = dt[0];
 #pragma unroll
     for (int t = 1; t < RB; t++)
       if (g == t) own = dt[t];
-    if constexpr (DK == F32COS) own = 1.0f - (SCR == SCR_FP8 ? tr.z * own : own);
-    const float eps = screen_eps<DK>(own, gam, tr.x, np, DK == F32COS ? tr.y : 0.0f);
+    float eps;
+    if constexpr (kIntDot) {
+      own = 1.0f - (p_scale * tr.z) * own;
+      eps = screen_eps_i8(gam, p_err, np, tr.x, tr.y);
+    } else {
+      if constexpr (DK == F32COS) own = 1.0f - (SCR == SCR_FP8 ? tr.z * own : own);
+      eps = screen_eps<DK>(own, gam, tr.x, np, DK == F32COS ? tr.y : 0.0f);
+    }
     const bool keep = mine && !(own - eps > w);
     wave_sync();  // every read of this round's ids precedes the compaction
     const uint64_t m = ballot(keep);
@@ -968,8 +1015,16 @@ k_beam(BeamArgs A) {
     uint32_t qn = 0;
     if constexpr (DK == U8L2) qn = group_sum_u32<L>(u8_selfdot<L, NCH>(qc));
     float qnorm = 0.0f;  // |p| for the cosine screen margin
-    if constexpr (SCR != SCR_NONE && DK == F32COS)
-      qnorm = reinterpret_cast<const float4*>(A.xs + (size_t)p * A.xs_stride + A.xs_tail)->y;
+    float qerr = 0.0f, qscale = 0.0f;
+    NarrowChunks<NCH, SCR == SCR_NONE ? SCR_FP8 : SCR> qcodes{};  // the point's own codes (int8 cosine)
+    if constexpr (SCR != SCR_NONE && DK == F32COS) {
+      const uint8_t* prow = A.xs + (size_t)p * A.xs_stride;
+      const float4 ptr = *reinterpret_cast<const float4*>(prow + A.xs_tail);
+      qnorm = ptr.y;
+      qerr = ptr.x;
+      qscale = ptr.z;
+      if constexpr (SCR == SCR_INT8) load_narrow<L, NCH, SCR>(qcodes, prow, X.Q, g);
+    }
 
     for (int i = lane; i < HSLOTS; i += 64) S.htab[i] = FG_NONE;
     if (lane == 0) S.nspill = 0;
@@ -1092,7 +1147,7 @@ k_beam(BeamArgs A) {
         if constexpr (SCR != SCR_NONE) {
           if (bsize == ef) {  // a full beam: its worst exact distance bounds entry
             const float w = ord_to_f32(key_hi(S.bkeys[cur][ef - 1]));
-            const int nx = screen_filter<DK, L, NCH, SCR>(A, qc, qnorm, S.sid, nnew, w);
+            const int nx = screen_filter<DK, L, NCH, SCR>(A, qc, qnorm, qcodes, qerr, qscale, S.sid, nnew, w);
             my_rej += (unsigned long long)(nnew - nx);
             nnew = nx;
             FG_TICK(8);

@@ -90,6 +90,7 @@ static void* pick_kernel(const Shape& s, int ef, bool search, int hslots, int sc
   if (!search && screen == SCR_NONE && (hslots == 512 || hslots == 1024)) return pick_small(s.dk, s.Q, ef, hslots);
   if (screen == SCR_BF16) return search ? nullptr : pick_screen_bf16(s.dk, s.Q, ef, hslots);
   if (screen == SCR_FP8) return search ? nullptr : pick_screen_fp8(s.dk, s.Q, ef, hslots);
+  if (screen == SCR_INT8) return search ? nullptr : pick_screen_int8(s.dk, s.Q, ef, hslots);
   return search ? pick<true>(s.dk, s.Q, ef, hslots) : pick<false>(s.dk, s.Q, ef, hslots);
 }
 

@@ -58,6 +58,7 @@ constexpr int kBeamLog = 16;
 void* pick_log(int dk, int Q, int ef);
 void* pick_screen_bf16(int dk, int Q, int ef, int hslots);
 void* pick_screen_fp8(int dk, int Q, int ef, int hslots);
+void* pick_screen_int8(int dk, int Q, int ef, int hslots);
 
 // Narrow copies for the screened harvest (fg_screen.hip): row stride in
 // bytes (whole 128-byte lines), the offset of each row's 16-byte trailer

@@ -6,7 +6,8 @@
 // One wave per row.  bfloat16: round to nearest even.  fp8-e4m3 (OCP): the
 // row is scaled by the power of two 2^k that brings its largest magnitude
 // to at most 448, converted by the hardware, and read back as
-// code * 2^-k.  For every row the norm of the actual error |u^ - u| and the
+// code * 2^-k; int8: codes rint(x / s) with s = fl(max|x| / 127), read
+// back as fl(code * s).  For every row the norm of the actual error |u^ - u| and the
 // norm |u| are bounded from above in float32 (no float64 on the device): each
 // element error is exact in float32, the squares of the row's elements and
 // errors are summed after scaling by a power of two that keeps them below
@@ -100,6 +101,10 @@ __global__ void __launch_bounds__(256) k_make_screen(const uint8_t* x, int64_t s
       scale = ldexpf(1.0f, k);
       inv = ldexpf(1.0f, -k);
     }
+    if constexpr (SCR == SCR_INT8) {  // symmetric: codes rint(x / s) in [-127, 127]
+      scale = mx / 127.0f;
+      inv = scale;  // the trailer's factor: a code reads back as fl(code * s)
+    }
     float e2 = 0.0f, n2 = 0.0f;
     for (int c = lane; c < C; c += 64) {
       const float4 v = *reinterpret_cast<const float4*>(row + 4 * c);
@@ -127,6 +132,16 @@ __global__ void __launch_bounds__(256) k_make_screen(const uint8_t* x, int64_t s
           *reinterpret_cast<uint2*>(at) = w;
           *reinterpret_cast<uint2*>(at + 32) = wl;
         }
+      } else if constexpr (SCR == SCR_INT8) {
+        uint32_t w = 0;
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          float q8 = scale > 0.0f ? __builtin_rintf(a[t] / scale) : 0.0f;
+          q8 = fminf(fmaxf(q8, -127.0f), 127.0f);
+          back[t] = q8 * scale;
+          w |= ((uint32_t)(int)q8 & 0xFFu) << (8 * t);
+        }
+        *reinterpret_cast<uint32_t*>(xs + i * xs_stride + 4 * (int64_t)c) = w;
       } else {
         int w = __builtin_amdgcn_cvt_pk_fp8_f32(a[0] * scale, a[1] * scale, 0, false);
         w = __builtin_amdgcn_cvt_pk_fp8_f32(a[2] * scale, a[3] * scale, w, true);
@@ -141,7 +156,10 @@ __global__ void __launch_bounds__(256) k_make_screen(const uint8_t* x, int64_t s
 #pragma unroll
       for (int t = 0; t < 4; t++) {
         // back and a are within a factor of two of each other (or back is
-        // zero), so their difference is exact in float32 (Sterbenz)
+        // zero), so their difference is exact in float32 (Sterbenz; int8: a
+        // code q != 0 comes from fl(x / s) > |q| - 1/2 >= 1/2, ties going
+        // to even, so |x| > |q| s / 2 for |q| = 1 and within 0.8..1.34 of
+        // fl(q s) for larger |q|)
         const float e = ldexpf(back[t] - a[t], -ex), y = ldexpf(a[t], -ex);
         e2 = __builtin_fmaf(e, e, e2);
         n2 = __builtin_fmaf(y, y, n2);
@@ -192,6 +210,9 @@ hipError_t make_screen(const Shape& s, int screen, uint8_t* xs, float* err, floa
   if (screen == SCR_BF16)
     k_make_screen<SCR_BF16><<<(unsigned)blocks, 256, 0, st>>>(s.x, s.stride, s.n, s.d, xs, xst, tail, err, norm, sinv,
                                                               sp, split_stride(s.d));
+  else if (screen == SCR_INT8)
+    k_make_screen<SCR_INT8><<<(unsigned)blocks, 256, 0, st>>>(s.x, s.stride, s.n, s.d, xs, xst, tail, err, norm,
+                                                              sinv, nullptr, 0);
   else
     k_make_screen<SCR_FP8><<<(unsigned)blocks, 256, 0, st>>>(s.x, s.stride, s.n, s.d, xs, xst, tail, err, norm, sinv,
                                                              nullptr, 0);

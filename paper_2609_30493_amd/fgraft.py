@@ -39,7 +39,7 @@ class fg_params(C.Structure):
                 ("waves_per_cu", C.c_uint32), ("lanes_per_row", C.c_uint32)]
 
 
-SCREEN_NONE, SCREEN_BF16, SCREEN_FP8E4M3, SCREEN_BF16_PRUNE = 0, 1, 2, 3
+SCREEN_NONE, SCREEN_BF16, SCREEN_FP8E4M3, SCREEN_BF16_PRUNE, SCREEN_INT8 = 0, 1, 2, 3, 4
 
 
 class fg_csr(C.Structure):

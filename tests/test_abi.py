@@ -66,8 +66,9 @@ def test_screen_row_bytes_without_gpu():
     lib.fg_screen_row_bytes.restype = ctypes.c_int64
     lib.fg_screen_row_bytes.argtypes = [ctypes.c_int32, ctypes.c_uint32]
     for d in (68, 96, 100, 128, 256, 260, 512, 960, 1024):
-        for kind, codes in ((1, (2 * d + 31) // 32 * 32), (2, (d + 15) // 16 * 16)):
+        for kind, codes in ((1, (2 * d + 31) // 32 * 32), (2, (d + 15) // 16 * 16), (4, (d + 15) // 16 * 16)):
             rb = lib.fg_screen_row_bytes(d, kind)
             assert rb % 128 == 0 and codes + 16 <= rb < codes + 16 + 128, (d, kind, rb)
     assert lib.fg_screen_row_bytes(100, 1) == 256 and lib.fg_screen_row_bytes(100, 2) == 128
     assert lib.fg_screen_row_bytes(0, 1) == 0 and lib.fg_screen_row_bytes(100, 7) == 0
+    assert lib.fg_screen_row_bytes(100, 3) == 0  # the split tiles have no narrow search copy

@@ -87,6 +87,8 @@ def test_graph_shape_must_match(lib):
     (dict(d=64), F.SCREEN_FP8E4M3, "64 < d <= 1024"),
     (dict(d=1028), F.SCREEN_BF16, "64 < d <= 1024"),
     (dict(d=100), F.SCREEN_BF16_PRUNE, "256 < d <= 1024"),
+    (dict(dtype=1, d=128), F.SCREEN_INT8, "FG_F32 data only"),
+    (dict(d=64), F.SCREEN_INT8, "64 < d <= 1024"),
 ])
 def test_unsupported_screens_are_refused(lib, dkw, screen, msg):
     rc, err = build(lib, data(**dkw), params(screen=screen), graph())

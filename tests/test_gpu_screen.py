@@ -129,6 +129,31 @@ def test_screen_copy_fp8_codes_decode_per_ocp_e4m3():
     _check_row_layout(F, xs, err, nrm, sinv, d, F.SCREEN_FP8E4M3)
 
 
+def test_screen_copy_int8_codes_and_error_norms():
+    """int8 codes rint(x / s) clamped to [-127, 127], s = fl(max|x| / 127)
+    in float32, read back as fl(code * s); the trailer's factor is s."""
+    F = _lib()
+    n, d = 300, 100
+    x = _rows(n, d, 3)
+    data = F.make_data(dev(x))
+    xs, err, nrm, sinv = F.screen_copy(data, F.SCREEN_INT8)
+    torch.cuda.synchronize()
+    codes = xs.cpu().numpy()[:, :d].view(np.int8).astype(np.int64)
+    mx = np.abs(x).max(1).astype(np.float32)
+    s = (mx / np.float32(127)).astype(np.float32)
+    assert np.array_equal(sinv.cpu().numpy(), s)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        want = np.where(s[:, None] > 0, np.clip(np.rint((x / s[:, None]).astype(np.float32)), -127, 127), 0)
+    assert np.array_equal(codes, want.astype(np.int64))
+    back = (codes.astype(np.float32) * s[:, None]).astype(np.float32).astype(np.float64)
+    e_true = np.sqrt(((back - x.astype(np.float64)) ** 2).sum(1))
+    n_true = np.sqrt((x.astype(np.float64) ** 2).sum(1))
+    e_gpu, n_gpu = err.cpu().numpy().astype(np.float64), nrm.cpu().numpy().astype(np.float64)
+    assert np.all(e_gpu >= e_true) and np.all(e_gpu <= _loosest(e_true, x))
+    assert np.all(n_gpu >= n_true) and np.all(n_gpu <= _loosest(n_true, x))
+    _check_row_layout(F, xs, err, nrm, sinv, d, F.SCREEN_INT8)
+
+
 SCREEN_BUILDS = [
     # name, data, metric, T, ef, R, B
     ("powerlaw-d96-5000", lambda: gen.powerlaw_f32(5000, 96, 40, 11), "l2", 8, 64, 32, 4),
@@ -159,7 +184,7 @@ def test_screened_builds_equal_unscreened_and_oracle(fgo, case):
     h0, g0, c0, k0 = _build(F, x, metric, T, ef, R, B, F.SCREEN_NONE)
     want = fgo.build_graph(fgo.Data(x, metric=metric), 42, fgo.params(T, ef, R, 1.2, B, 0, 8))
     assert h0 == want["hash"]
-    for scr in (F.SCREEN_BF16, F.SCREEN_FP8E4M3):
+    for scr in (F.SCREEN_BF16, F.SCREEN_FP8E4M3, F.SCREEN_INT8):
         h, g, c, k = _build(F, x, metric, T, ef, R, B, scr)
         say(f"  screen={scr} rejected {k['screen_rejected']} of {k['harvest_evals']}")
         assert h == h0
@@ -181,7 +206,7 @@ def test_screened_builds_at_every_table_size(table):
         x = np.ascontiguousarray(mk().astype(np.float32))
         say(f"screened build {name} table={table}")
         h0, g0, c0, k0 = _build(F, x, metric, T, ef, R, B, F.SCREEN_NONE)
-        for scr in (F.SCREEN_BF16, F.SCREEN_FP8E4M3):
+        for scr in (F.SCREEN_BF16, F.SCREEN_FP8E4M3, F.SCREEN_INT8):
             h, g, c, k = _build(F, x, metric, T, ef, R, B, scr, table)
             assert h == h0 and np.array_equal(g, g0) and np.array_equal(c, c0), (name, scr)
             for key in ("harvest_evals", "expansions", "prune_evals", "finalize_evals", "scaffold_evals"):
@@ -197,7 +222,7 @@ def test_screened_harvest_block_equals_unscreened(fgo):
     r, parents, off, ids, _ = fgo.scaffold(D, 42, T)
     data = F.make_data(dev(x))
     out = []
-    for scr in (0, 1, 2):
+    for scr in (0, 1, 2, 4):
         params = F.make_params(T, ef, R, 1.2, B, screen=scr)
         ws = F.alloc_workspace(data, params)
         S = F.csr(dev(off.view(np.int64)), dev(ids.view(np.int32)), int(off[-1]))
@@ -231,7 +256,7 @@ def test_screen_argument_errors():
                                                              empty_u32(4), 4),
                       torch.empty(1 << 26, dtype=torch.uint8, device="cuda"))
     assert e.value.code == F.FG_EUNSUPPORTED
-    p = F.make_params(4, 32, 16, 1.2, 2, screen=4)
+    p = F.make_params(4, 32, 16, 1.2, 2, screen=5)  # no such fg_screen
     with pytest.raises(F.FgError) as e:
         F.build_graph(d64, 1, p, F.make_graph(empty_u32(500, 16), empty_u32(500), empty_u32(500),
                                               empty_u32(4), 4), torch.empty(1 << 20, dtype=torch.uint8,

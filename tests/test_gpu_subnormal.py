@@ -36,7 +36,7 @@ def test_subnormal_square_rows_match_oracle_in_every_form(fgo, d, log2scale):
     sq = (x.astype(np.float64) ** 2).sum(1)
     say(f"subnormal-range rows d={d} scale 2^{log2scale}: median |x|^2 = {np.median(sq):.3e}")
     want = fgo.build_graph(fgo.Data(x), 42, fgo.params(T, ef, R, 1.2, B, 0, 8))
-    forms = [F.SCREEN_NONE, F.SCREEN_BF16, F.SCREEN_FP8E4M3, F.SCREEN_BF16_PRUNE]
+    forms = [F.SCREEN_NONE, F.SCREEN_BF16, F.SCREEN_FP8E4M3, F.SCREEN_INT8, F.SCREEN_BF16_PRUNE]
     for scr in forms:
         h, g, c, k = _build(F, x, "l2", T, ef, R, B, scr)
         say(f"  screen={scr}: rechecks {k['prune_rechecks']}, rejected {k['screen_rejected']}")

@@ -45,6 +45,38 @@ def fp8_back(u):
     return (grid[idx] * 2.0 ** -k).astype(np.float32)
 
 
+def int8_codes(u):
+    """Codes rint(u / s) in [-127, 127] with s = fl(max|u| / 127), all in
+    float32 as the copy kernel computes them."""
+    u = u.astype(np.float32)
+    s = np.float32(np.abs(u).max() / np.float32(127))
+    if s == 0:
+        return np.zeros(u.shape, np.int64), np.float32(0)
+    q = np.clip(np.rint((u / s).astype(np.float32)), -127, 127).astype(np.int64)
+    return q, s
+
+
+def int8_back(u):
+    q, s = int8_codes(u)
+    return (q.astype(np.float32) * s).astype(np.float32)
+
+
+def margin_i8(E_p, np_, E_u, nu, d):
+    """Cosine over int8 codes of both rows (the kernel's exact integer dot)."""
+    gc = (d // 16 + 8) * U / (1 - (d // 16 + 8) * U)
+    Epp, Eup = E_p + U * (np_ + E_p), E_u + U * (nu + E_u)
+    P, Uu = np_ + Epp, nu + Eup
+    return Epp * nu + P * Eup + (gc + 4 * U) * P * Uu + 4 * U * (1 + P * Uu)
+
+
+def screened_i8(p, u):
+    """1 - fl(fl(s_p s_u) I), I the exact integer dot product of the codes."""
+    qp, sp = int8_codes(p)
+    qu, su = int8_codes(u)
+    I = np.float32(int((qp * qu).sum()))
+    return float(np.float32(np.float32(1) - np.float32(np.float32(sp * su) * I)))
+
+
 def screened(p, ub, metric, mode):
     """Screened value in float32, several summation orders."""
     if metric == "l2":
@@ -99,13 +131,26 @@ def pairs(metric, rng, d):
 
 
 @pytest.mark.parametrize("metric", ["l2", "cosine"])
-@pytest.mark.parametrize("kind", ["bf16", "fp8"])
+@pytest.mark.parametrize("kind", ["bf16", "fp8", "int8"])
 @pytest.mark.parametrize("d", [68, 100, 960])
 def test_margin_bounds_exact_distance(fgo, metric, kind, d):
-    rng = np.random.default_rng(d * 3 + (kind == "fp8") + 7 * (metric == "cosine"))
+    rng = np.random.default_rng(d * 3 + (kind == "fp8") + 7 * (metric == "cosine") + 11 * (kind == "int8"))
     worst = 0.0
     for p, u in pairs(metric, rng, d):
-        ub = bf16_back(u) if kind == "bf16" else fp8_back(u)
+        if kind == "int8" and metric == "cosine":
+            # both rows' codes, integer dot product (the kernel's form)
+            E_p = np.sqrt(((int8_back(p).astype(np.float64) - p.astype(np.float64)) ** 2).sum())
+            E_u = np.sqrt(((int8_back(u).astype(np.float64) - u.astype(np.float64)) ** 2).sum())
+            np_ = np.sqrt((p.astype(np.float64) ** 2).sum())
+            nu = np.sqrt((u.astype(np.float64) ** 2).sum())
+            exact = float(fgo.dist(fgo.Data(np.stack([p, u]), metric=metric), 0, 1))
+            dt = screened_i8(p, u)
+            eps = margin_i8(E_p, np_, E_u, nu, d)
+            assert abs(exact - dt) <= eps, (exact, dt, eps)
+            if eps > 0:
+                worst = max(worst, abs(dt - exact) / eps)
+            continue
+        ub = {"bf16": bf16_back, "fp8": fp8_back, "int8": int8_back}[kind](u)
         E = np.sqrt(((ub.astype(np.float64) - u.astype(np.float64)) ** 2).sum())
         np_ = np.sqrt((p.astype(np.float64) ** 2).sum())
         nu = np.sqrt((u.astype(np.float64) ** 2).sum())
