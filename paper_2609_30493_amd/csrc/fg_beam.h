@@ -265,52 +265,67 @@ __device__ __forceinline__ int group_dot_i8(const NarrowChunks<NCH, SCR_INT8>& p
 // least dt - eps, for a screened value dt (standard rounding-error analysis,
 // unit roundoff u = 2^-24; gs bounds the screened sum's relative error over
 // d + 12 roundings, gc the declared order's over d/16 + 8):
-//   squared L2: with A = sqrt(dt / (1 - gs)) >= |p - u^|, |p - u| >= A' - E
-//     where E = |u^ - u|, so exact >= dt - (gs + gc) dt - 2 A E;
+//   squared L2: with A = sqrt((dt + t) / (1 - gs)) >= |p - u^|,
+//     |p - u| >= |p - u^| - E where E = |u^ - u|, so that
+//     exact >= dt - (gs + gc) dt - 2 A E - t;
 //   cosine: |<p,u^> - <p,u>| <= |p| E, both sums' errors are within
-//     (gs + gc) |p| (|u| + E), and the two roundings of 1 - s add
-//     2^-23 (1 + |p| (|u| + E)).
-// The result is doubled, which also covers the rounding of eps itself.
+//     (gs + gc) |p| (|u| + E) + t, and the two roundings of 1 - s, with
+//     the fp8 copy's power-of-two factor f, add 4u (1 + |p| (|u| + E)).
+// t covers underflow: float32 subnormals are kept (IEEE mode, as built), so
+// a product or fused multiply-add that underflows errs by at most 2^-150,
+// d of them per sum: t = d 2^-149 for squared L2's two sums; for cosine
+// t = d 2^-149 (1 + max(1, f) + |p|), the screened sum's errors scaled by
+// f, and the fp8 read-back's underflow (at most 2^-150 per element) against
+// |p|.  The result is raised by 2^-20 of itself, which covers the rounding
+// of its own few operations (each at most u).
 struct ScreenGammas {
   float gs, gc;
+  float t;  // d 2^-149
 };
 
 __device__ __forceinline__ ScreenGammas screen_gammas(int d) {
   const float u = 5.9604645e-08f;  // 2^-24
-  return {(d + 12) * u / (1.0f - (d + 12) * u), (d / 16 + 8) * u / (1.0f - (d / 16 + 8) * u)};
+  return {(d + 12) * u / (1.0f - (d + 12) * u), (d / 16 + 8) * u / (1.0f - (d / 16 + 8) * u),
+          (float)d * 1.4012985e-45f};
 }
 
+constexpr float kEpsRaise = 1.0f + 9.5367432e-07f;  // 1 + 2^-20
+
 template <int DK>
-__device__ __forceinline__ float screen_eps(float dt, ScreenGammas k, float E, float np, float nu) {
+__device__ __forceinline__ float screen_eps(float dt, ScreenGammas k, float E, float np, float nu, float f) {
   const float u = 5.9604645e-08f;  // 2^-24
   const float gs = k.gs, gc = k.gc;
   float eps;
   if constexpr (DK == F32L2) {
     const float dd = dt > 0.0f ? dt : 0.0f;
-    const float A = __builtin_sqrtf(dd / (1.0f - gs)) * (1.0f + 4.0f * u);
-    eps = (gs + gc) * dd + 2.0f * A * E;
+    const float A = __builtin_sqrtf((dd + k.t) / (1.0f - gs)) * (1.0f + 4.0f * u);
+    eps = (gs + gc) * dd + 2.0f * A * E + k.t;
   } else {
     const float pu = np * (nu + E);
-    eps = np * E + (gs + gc) * pu + 2.0f * u * 2.0f * (1.0f + pu);
+    eps = np * E + (gs + gc) * pu + 4.0f * u * (1.0f + pu) + k.t * (1.0f + fmaxf(1.0f, f) + np);
   }
-  return 2.0f * eps;
+  return eps * kEpsRaise;
 }
 
 // The same for cosine over int8 codes of both rows: dt = 1 - fl(fl(s_p s_u) I)
 // with I the exact integer dot product, so <p^,u^> = s_p s_u I with p^, u^
 // the codes times their scales in exact arithmetic.  Their distances from p
-// and u are at most E' = E + u (|x| + E) (E bounds the distance from the
-// copy read back with one rounding per element):
+// and u are at most E' = E + u (|x| + E) + d 2^-150 (E bounds the distance
+// from the copy read back with one rounding per element, which may also
+// underflow):
 //   |<p,u> - <p^,u^>| <= E'_p |u| + |p^| E'_u, |p^| <= |p| + E'_p = P,
 //   |u^| <= U; the two products round by at most 2.0001 u P U, 1 - x by
 //   u (1 + P U); the declared order's sum errs by gc |p||u| and its 1 - s
-//   by u (1 + |p||u|).  Doubled as above.
+//   by u (1 + |p||u|).  Underflow: fl(s_p s_u) errs by at most 2^-150,
+//   times |I| <= 127^2 d, and the declared sum's d operations by 2^-150
+//   each: below d 2^-136 together.  Raised by 2^-20 of itself as above.
 __device__ __forceinline__ float screen_eps_i8(ScreenGammas k, float Ep, float np, float Eu, float nu) {
   const float u = 5.9604645e-08f;  // 2^-24
-  const float Epp = Ep + u * (np + Ep), Eup = Eu + u * (nu + Eu);
+  const float fl = 0.5f * k.t;       // d 2^-150
+  const float Epp = Ep + u * (np + Ep) + fl, Eup = Eu + u * (nu + Eu) + fl;
   const float P = np + Epp, U = nu + Eup;
-  const float eps = Epp * nu + P * Eup + (k.gc + 4.0f * u) * P * U + 4.0f * u * (1.0f + P * U);
-  return 2.0f * eps;
+  const float eps = Epp * nu + P * Eup + (k.gc + 4.0f * u) * P * U + 4.0f * u * (1.0f + P * U) + 8192.0f * k.t;
+  return eps * kEpsRaise;
 }
 
 // Screen the cnt new ids in ids_lds (cnt <= 256) against the beam's worst
@@ -376,9 +391,186 @@ __device__ __forceinline__ int screen_filter(const BeamArgs& A, const Chunks<L, 
       eps = screen_eps_i8(gam, p_err, np, tr.x, tr.y);
     } else {
       if constexpr (DK == F32COS) own = 1.0f - (SCR == SCR_FP8 ? tr.z * own : own);
-      eps = screen_eps<DK>(own, gam, tr.x, np, DK == F32COS ? tr.y : 0.0f);
+      eps = screen_eps<DK>(own, gam, tr.x, np, DK == F32COS ? tr.y : 0.0f, SCR == SCR_FP8 ? tr.z : 1.0f);
     }
     const bool keep = mine && !(own - eps > w);
+    wave_sync();  // every read of this round's ids precedes the compaction
+    const uint64_t m = ballot(keep);
+    if (keep) ids_lds[kept + popc64(m & lanes_below())] = myid;
+    kept += popc64(m);
+    wave_sync();
+  }
+  return kept;
+}
+
+// Rows of 16 chunks per lane and more (d > 256): the whole wave screens a
+// narrow row, lane l taking its elements [16 l, 16 l + 16) -- one 16-byte
+// load of fp8 or int8 codes, two of bfloat16 -- so a round keeps kWideRows
+// rows in flight in 4 (8) registers each, where the group layout above
+// holds a row in 16 (32) and the kernel's register budget allowed only one
+// row per group (four per wave).  The point's own elements in this layout
+// are read again at each call from its rows (cache hits, issued with the
+// first round's loads), so nothing stays live across the search.  Lane 8t
+// loads row t's trailer and decides row t; the eight partial sums are
+// reduced together (three halving exchanges, then three plain ones), in an
+// order of their own, which the margins allow.
+constexpr int kWideRows = 8;
+
+template <typename T>
+__device__ __forceinline__ T reduce_wide_rows(const T (&v)[kWideRows]) {
+  const int lane = lane_id();
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+  T w4[4], w2[2];
+#pragma unroll
+  for (int t = 0; t < 4; t++) {  // w4[t]: row t + 4 b5
+    const T send = b5 ? v[t] : v[t + 4], keep = b5 ? v[t + 4] : v[t];
+    w4[t] = keep + __shfl_xor(send, 32, 64);
+  }
+#pragma unroll
+  for (int t = 0; t < 2; t++) {  // w2[t]: row t + 2 b4 + 4 b5
+    const T send = b4 ? w4[t] : w4[t + 2], keep = b4 ? w4[t + 2] : w4[t];
+    w2[t] = keep + __shfl_xor(send, 16, 64);
+  }
+  const T send = b3 ? w2[0] : w2[1], keep = b3 ? w2[1] : w2[0];
+  T s = keep + __shfl_xor(send, 8, 64);  // row b3 + 2 b4 + 4 b5 = lane / 8
+  s = s + __shfl_xor(s, 4, 64);
+  s = s + __shfl_xor(s, 2, 64);
+  s = s + __shfl_xor(s, 1, 64);
+  return s;
+}
+
+template <int SCR>
+struct WideRow {
+  uint4 w[SCR == SCR_BF16 ? 2 : 1];
+};
+
+// Lane l's 16 codes of a narrow row (zero for chunks at or past Q).
+template <int SCR>
+__device__ __forceinline__ void load_wide(WideRow<SCR>& r, const uint8_t* srow, int Q, int lane) {
+  const int q0 = 4 * lane;
+#pragma unroll
+  for (int h = 0; h < (SCR == SCR_BF16 ? 2 : 1); h++) {
+    uint4 v = make_uint4(0, 0, 0, 0);
+    const int qh = q0 + 2 * h;  // first chunk of this 16-byte word (bfloat16: two chunks per word)
+    if (qh < Q) v = *reinterpret_cast<const uint4*>(srow + (SCR == SCR_BF16 ? 32 : 16) * (size_t)lane + 16 * h);
+    if constexpr (SCR == SCR_BF16) {
+      if (qh + 1 >= Q) v.z = v.w = 0u;
+    } else {
+      if (q0 + 1 >= Q) v.y = 0u;
+      if (q0 + 2 >= Q) v.z = 0u;
+      if (q0 + 3 >= Q) v.w = 0u;
+    }
+    r.w[h] = v;
+  }
+}
+
+// Chunk k (four elements) of a wide row: its codes as float32, scaled by
+// sinv element by element for squared L2 over fp8 or int8.
+template <int DK, int SCR>
+__device__ __forceinline__ float4 wide_chunk(const WideRow<SCR>& r, int k, float sinv) {
+  const uint4& v = r.w[SCR == SCR_BF16 ? k / 2 : 0];
+  if constexpr (SCR == SCR_BF16) {
+    const uint32_t w0 = (k & 1) ? v.z : v.x, w1 = (k & 1) ? v.w : v.y;
+    return make_float4(__uint_as_float(w0 << 16), __uint_as_float(w0 & 0xFFFF0000u), __uint_as_float(w1 << 16),
+                       __uint_as_float(w1 & 0xFFFF0000u));
+  } else {
+    const int w = (int)(k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w);
+    if constexpr (SCR == SCR_INT8) {
+      return make_float4((float)((w << 24) >> 24) * sinv, (float)((w << 16) >> 24) * sinv,
+                         (float)((w << 8) >> 24) * sinv, (float)(w >> 24) * sinv);
+    } else {
+      const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8(w, false);
+      const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8(w, true);
+      if constexpr (DK == F32L2) return make_float4(lo[0] * sinv, lo[1] * sinv, hi[0] * sinv, hi[1] * sinv);
+      return make_float4(lo[0], lo[1], hi[0], hi[1]);
+    }
+  }
+}
+
+// The screen of screen_filter for rows of 16 chunks per lane and more, in
+// the wave-per-row layout: qrow is the point's float32 row, prow its narrow
+// row (whose codes the int8 cosine screen takes).  Same contract and margins.
+template <int DK, int SCR>
+__device__ __forceinline__ int screen_filter_wide(const BeamArgs& A, const uint8_t* qrow, const uint8_t* prow,
+                                                  float np, float p_err, float p_scale, uint32_t* ids_lds, int cnt,
+                                                  float w) {
+  constexpr bool kIntDot = SCR == SCR_INT8 && DK == F32COS;
+  const int lane = lane_id();
+  const int Q = A.Q;
+  const ScreenGammas gam = screen_gammas(A.d);
+  float4 qv[4];
+  uint4 qcode = make_uint4(0, 0, 0, 0);
+  if constexpr (kIntDot) {
+    WideRow<SCR> pr;
+    load_wide<SCR>(pr, prow, Q, lane);
+    qcode = pr.w[0];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int q = 4 * lane + k;
+      qv[k] = q < Q ? *reinterpret_cast<const float4*>(qrow + 16 * (size_t)q) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+  const int myt = lane >> 3;
+  int kept = 0;
+  for (int r0 = 0; r0 < cnt; r0 += kWideRows) {
+    uint32_t id[kWideRows];
+#pragma unroll
+    for (int t = 0; t < kWideRows; t++) id[t] = ids_lds[r0 + t < cnt ? r0 + t : r0];
+    const bool dec = (lane & 7) == 0 && r0 + myt < cnt;
+    const uint32_t myid = ids_lds[r0 + myt < cnt ? r0 + myt : r0];
+    // every row's loads are issued before any is used
+    const float4 tr = *reinterpret_cast<const float4*>(A.xs + (size_t)myid * A.xs_stride + A.xs_tail);
+    WideRow<SCR> rw[kWideRows];
+#pragma unroll
+    for (int t = 0; t < kWideRows; t++) load_wide<SCR>(rw[t], A.xs + (size_t)id[t] * A.xs_stride, Q, lane);
+    float own;
+    float eps;
+    if constexpr (kIntDot) {
+      int acc[kWideRows];
+#pragma unroll
+      for (int t = 0; t < kWideRows; t++) {
+        const uint4 v = rw[t].w[0];
+        int s = __builtin_amdgcn_sdot4((int)qcode.x, (int)v.x, 0, false);
+        s = __builtin_amdgcn_sdot4((int)qcode.y, (int)v.y, s, false);
+        s = __builtin_amdgcn_sdot4((int)qcode.z, (int)v.z, s, false);
+        acc[t] = __builtin_amdgcn_sdot4((int)qcode.w, (int)v.w, s, false);
+      }
+      own = 1.0f - (p_scale * tr.z) * (float)reduce_wide_rows<int>(acc);
+      eps = screen_eps_i8(gam, p_err, np, tr.x, tr.y);
+    } else {
+      float acc[kWideRows];
+#pragma unroll
+      for (int t = 0; t < kWideRows; t++) {
+        // squared L2 over fp8 or int8 codes scales each element by its
+        // row's factor, which lane 8t loaded
+        const float sinv = ((SCR == SCR_FP8 || SCR == SCR_INT8) && DK == F32L2)
+                               ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tr.z), 8 * t))
+                               : 1.0f;
+        float a = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+          const float4 xb = wide_chunk<DK, SCR>(rw[t], k, sinv);
+          if constexpr (DK == F32L2) {
+            const float d0 = qv[k].x - xb.x, d1 = qv[k].y - xb.y, d2 = qv[k].z - xb.z, d3 = qv[k].w - xb.w;
+            a = __builtin_fmaf(d0, d0, a);
+            a = __builtin_fmaf(d1, d1, a);
+            a = __builtin_fmaf(d2, d2, a);
+            a = __builtin_fmaf(d3, d3, a);
+          } else {
+            a = __builtin_fmaf(qv[k].x, xb.x, a);
+            a = __builtin_fmaf(qv[k].y, xb.y, a);
+            a = __builtin_fmaf(qv[k].z, xb.z, a);
+            a = __builtin_fmaf(qv[k].w, xb.w, a);
+          }
+        }
+        acc[t] = a;
+      }
+      own = reduce_wide_rows<float>(acc);
+      if constexpr (DK == F32COS) own = 1.0f - (SCR == SCR_FP8 ? tr.z * own : own);
+      eps = screen_eps<DK>(own, gam, tr.x, np, DK == F32COS ? tr.y : 0.0f, SCR == SCR_FP8 ? tr.z : 1.0f);
+    }
+    const bool keep = dec && !(own - eps > w);
     wave_sync();  // every read of this round's ids precedes the compaction
     const uint64_t m = ballot(keep);
     if (keep) ids_lds[kept + popc64(m & lanes_below())] = myid;
@@ -1023,7 +1215,7 @@ k_beam(BeamArgs A) {
       qnorm = ptr.y;
       qerr = ptr.x;
       qscale = ptr.z;
-      if constexpr (SCR == SCR_INT8) load_narrow<L, NCH, SCR>(qcodes, prow, X.Q, g);
+      if constexpr (SCR == SCR_INT8 && NCH < 16) load_narrow<L, NCH, SCR>(qcodes, prow, X.Q, g);
     }
 
     for (int i = lane; i < HSLOTS; i += 64) S.htab[i] = FG_NONE;
@@ -1147,7 +1339,12 @@ k_beam(BeamArgs A) {
         if constexpr (SCR != SCR_NONE) {
           if (bsize == ef) {  // a full beam: its worst exact distance bounds entry
             const float w = ord_to_f32(key_hi(S.bkeys[cur][ef - 1]));
-            const int nx = screen_filter<DK, L, NCH, SCR>(A, qc, qnorm, qcodes, qerr, qscale, S.sid, nnew, w);
+            int nx;
+            if constexpr (NCH >= 16)
+              nx = screen_filter_wide<DK, SCR>(A, qrow, A.xs + (size_t)p * A.xs_stride, qnorm, qerr, qscale, S.sid,
+                                               nnew, w);
+            else
+              nx = screen_filter<DK, L, NCH, SCR>(A, qc, qnorm, qcodes, qerr, qscale, S.sid, nnew, w);
             my_rej += (unsigned long long)(nnew - nx);
             nnew = nx;
             FG_TICK(8);

@@ -159,6 +159,10 @@ SCREEN_BUILDS = [
     ("powerlaw-d96-5000", lambda: gen.powerlaw_f32(5000, 96, 40, 11), "l2", 8, 64, 32, 4),
     ("powerlaw-d256-4000", lambda: gen.powerlaw_f32(4000, 256, 40, 12), "l2", 8, 128, 32, 8),
     ("powerlaw-d960-3000", lambda: gen.powerlaw_f32(3000, 960, 60, 13), "l2", 8, 128, 64, 8),
+    # rows screened by the whole wave (more than 64 chunks): cosine, and a
+    # last lane holding one chunk of its four
+    ("cosine-d300-3000", lambda: gen.anisotropic_unit_f32(3000, 300, 40, 16), "cosine", 8, 128, 64, 8),
+    ("powerlaw-d260-3000", lambda: gen.powerlaw_f32(3000, 260, 40, 17), "l2", 8, 64, 32, 4),
     ("cosine-d100-5000", lambda: gen.anisotropic_unit_f32(5000, 100, 50, 14), "cosine", 8, 128, 64, 8),
     ("isotropic-d68-4000", lambda: gen.isotropic_f32(4000, 68, 8, 0.1, 15), "l2", 4, 256, 16, 2),
 ]
@@ -202,7 +206,8 @@ def test_screened_builds_at_every_table_size(table):
     the same graph and counters as the unscreened build, which the test
     above ties to the oracle."""
     F = _lib()
-    for name, mk, metric, T, ef, R, B in (SCREEN_BUILDS[0], SCREEN_BUILDS[1], SCREEN_BUILDS[3]):
+    picked = ("powerlaw-d96-5000", "powerlaw-d256-4000", "cosine-d100-5000", "cosine-d300-3000")
+    for name, mk, metric, T, ef, R, B in (c for c in SCREEN_BUILDS if c[0] in picked):
         x = np.ascontiguousarray(mk().astype(np.float32))
         say(f"screened build {name} table={table}")
         h0, g0, c0, k0 = _build(F, x, metric, T, ef, R, B, F.SCREEN_NONE)

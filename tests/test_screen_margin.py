@@ -2,7 +2,8 @@
 the standard model, unit roundoff 2^-24) against the oracle's exact distance
 in the declared float32 order: for random and adversarial pairs, the exact
 distance is never below the screened value minus the margin.  The margin is
-restated here from its derivation (the kernel uses twice this value)."""
+restated here from its derivation, underflow terms included (the kernel
+raises it by 2^-20 of itself for its own roundings)."""
 import numpy as np
 import pytest
 import torch
@@ -10,15 +11,20 @@ import torch
 U = 2.0 ** -24
 
 
-def margin(dt, d, E, np_, nu, metric):
+T149 = 2.0 ** -149  # the smallest float32 subnormal
+
+
+def margin(dt, d, E, np_, nu, metric, f=1.0):
+    """f: the fp8 copy's power-of-two factor, applied to the cosine sum."""
     gs = (d + 12) * U / (1 - (d + 12) * U)
     gc = (d // 16 + 8) * U / (1 - (d // 16 + 8) * U)
+    t = d * T149
     if metric == "l2":
         dd = max(dt, 0.0)
-        A = np.sqrt(dd / (1 - gs)) * (1 + 4 * U)
-        return (gs + gc) * dd + 2 * A * E
+        A = np.sqrt((dd + t) / (1 - gs)) * (1 + 4 * U)
+        return (gs + gc) * dd + 2 * A * E + t
     pu = np_ * (nu + E)
-    return np_ * E + (gs + gc) * pu + 4 * U * (1 + pu)
+    return np_ * E + (gs + gc) * pu + 4 * U * (1 + pu) + t * (1 + max(1.0, f) + np_)
 
 
 def bf16_back(u):
@@ -45,6 +51,15 @@ def fp8_back(u):
     return (grid[idx] * 2.0 ** -k).astype(np.float32)
 
 
+def fp8_factor(u):
+    """The power of two 2^-k that reads an fp8 code back (see fp8_back)."""
+    mx = np.abs(u.astype(np.float64)).max()
+    k = 0 if mx == 0 else int(np.floor(np.log2(448.0 / mx)))
+    while mx and np.ldexp(mx, k) > 448.0:
+        k -= 1
+    return 2.0 ** -k
+
+
 def int8_codes(u):
     """Codes rint(u / s) in [-127, 127] with s = fl(max|u| / 127), all in
     float32 as the copy kernel computes them."""
@@ -64,9 +79,10 @@ def int8_back(u):
 def margin_i8(E_p, np_, E_u, nu, d):
     """Cosine over int8 codes of both rows (the kernel's exact integer dot)."""
     gc = (d // 16 + 8) * U / (1 - (d // 16 + 8) * U)
-    Epp, Eup = E_p + U * (np_ + E_p), E_u + U * (nu + E_u)
+    fl = d * T149 / 2
+    Epp, Eup = E_p + U * (np_ + E_p) + fl, E_u + U * (nu + E_u) + fl
     P, Uu = np_ + Epp, nu + Eup
-    return Epp * nu + P * Eup + (gc + 4 * U) * P * Uu + 4 * U * (1 + P * Uu)
+    return Epp * nu + P * Eup + (gc + 4 * U) * P * Uu + 4 * U * (1 + P * Uu) + 8192 * d * T149
 
 
 def screened_i8(p, u):
@@ -127,6 +143,13 @@ def pairs(metric, rng, d):
         out = [(p / np.linalg.norm(p.astype(np.float64)), u / np.linalg.norm(u.astype(np.float64)))
                for p, u in out if np.linalg.norm(p) > 0 and np.linalg.norm(u) > 0]
         out = [(p.astype(np.float32), u.astype(np.float32)) for p, u in out]
+    # rows whose squares and products fall in the subnormal range (or below
+    # it), where the sums' underflow, not their rounding, decides the error
+    for ex in (-60, -64, -68, -72, -76):
+        for _ in range(6):
+            p = (rng.standard_normal(d) * 2.0 ** ex).astype(np.float32)
+            u = (p + rng.standard_normal(d) * 2.0 ** (ex - rng.uniform(0, 6))).astype(np.float32)
+            out.append((p, u))
     return out
 
 
@@ -158,7 +181,7 @@ def test_margin_bounds_exact_distance(fgo, metric, kind, d):
         exact = float(fgo.dist(D, 0, 1))
         for mode in ("seq", "rev", "pair"):
             dt = screened(p, ub, metric, mode)
-            eps = margin(dt, d, E, np_, nu, metric)
+            eps = margin(dt, d, E, np_, nu, metric, fp8_factor(u) if kind == "fp8" else 1.0)
             assert exact >= dt - eps, (mode, exact, dt, eps)
             if eps > 0:
                 worst = max(worst, (dt - exact) / eps)
