@@ -163,6 +163,8 @@ SCREEN_BUILDS = [
     # last lane holding one chunk of its four
     ("cosine-d300-3000", lambda: gen.anisotropic_unit_f32(3000, 300, 40, 16), "cosine", 8, 128, 64, 8),
     ("powerlaw-d260-3000", lambda: gen.powerlaw_f32(3000, 260, 40, 17), "l2", 8, 64, 32, 4),
+    # the largest rows (every lane holds four chunks) and the widest beam
+    ("powerlaw-d1024-2000", lambda: gen.powerlaw_f32(2000, 1024, 30, 18), "l2", 8, 256, 32, 4),
     ("cosine-d100-5000", lambda: gen.anisotropic_unit_f32(5000, 100, 50, 14), "cosine", 8, 128, 64, 8),
     ("isotropic-d68-4000", lambda: gen.isotropic_f32(4000, 68, 8, 0.1, 15), "l2", 4, 256, 16, 2),
 ]
