@@ -332,9 +332,9 @@ __device__ __forceinline__ float screen_eps_i8(ScreenGammas k, float Ep, float n
 // exact distance w: ids that cannot enter the beam are dropped, the others
 // are compacted to the front of ids_lds (in an order of their own: the
 // beam's merge sorts by key).  Returns their number.  A narrow row is a
-// quarter or half of the float32 row's bytes, so for rows of fewer than 16
-// chunks per lane twice as many rows are kept in flight per round as in
-// the exact gathers (longer rows: one per group).  Every row's loads of a
+// quarter or half of the float32 row's bytes, so twice as many rows are
+// kept in flight per round as in the exact gathers (rows of 16 chunks per
+// lane and more take screen_filter_wide below).  Every row's loads of a
 // round are issued before the first is used (with the loads inside the
 // per-row arithmetic the compiler waited on each row in turn, and the
 // screened harvest took 1.3-1.6x the plain one).  Lane g of a group owns
@@ -347,7 +347,8 @@ __device__ __forceinline__ int screen_filter(const BeamArgs& A, const Chunks<L, 
                                              uint32_t* ids_lds, int cnt, float w) {
   constexpr bool kIntDot = SCR == SCR_INT8 && DK == F32COS;  // the point's own codes against the row's
   constexpr int G = 64 / L;
-  constexpr int RB = (NCH >= 16) ? 1 : 32 / NCH;
+  static_assert(NCH < 16, "longer rows take screen_filter_wide");
+  constexpr int RB = 32 / NCH;
   static_assert(RB <= L, "a lane owns at most one row of a round");
   const int lane = lane_id();
   const int grp = lane / L, g = lane % L;
