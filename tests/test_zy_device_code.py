@@ -1,9 +1,12 @@
 """The device code the library ships (gfx950 code objects embedded in
 libfgraft.so, disassembled with the ROCm LLVM tools): no float64
 instruction anywhere (the precision form keeps every device computation in
-float32 or narrower; float64 exists only in the oracle on the host), and no
-packed-float32 VALU instruction (the build disables them).  The extraction
-and the disassembly run in a child process that reports a small summary."""
+float32 or narrower; float64 exists only in the oracle on the host), no
+packed-float32 VALU instruction (the build disables them), and every kernel
+keeping float32 subnormals (its descriptor's float32 denormal mode is 3, no
+flushing: the screen margins bound an underflowing operation's error by
+2^-150, which flushing to zero would exceed).  The extraction and the
+disassembly run in a child process that reports a small summary."""
 import json
 import os
 import shutil
@@ -43,15 +46,33 @@ while True:
             open(path, "wb").write(data[i + off:i + off + size])
             cos.append(path)
     pos = i + 1
+RE = os.path.join(os.path.dirname(objdump), "llvm-readelf")
 kernels, f64, pk = set(), set(), set()
+denorm32 = {}
 for co in cos:
+    # kernel descriptors (64 bytes, in .rodata): compute_pgm_rsrc1 at byte 48,
+    # float32 denormal mode in its bits 16-17
+    blob = open(co, "rb").read()
+    secs = {}  # section index -> (address, file offset)
+    for l in subprocess.run([RE, "-S", "-W", co], check=True, capture_output=True, text=True).stdout.splitlines():
+        m = re.match(r"\s*\[\s*(\d+)\]\s+(\S+)\s+\S+\s+([0-9a-f]+)\s+([0-9a-f]+)", l)
+        if m:
+            secs[m.group(1)] = (int(m.group(3), 16), int(m.group(4), 16))
+    for l in subprocess.run([RE, "--symbols", "-W", co], check=True, capture_output=True, text=True).stdout.splitlines():
+        f = l.split()
+        if len(f) >= 8 and f[-1].endswith(".kd"):
+            addr, off = secs[f[6]]
+            rs1 = struct.unpack_from("<I", blob, off + int(f[1], 16) - addr + 48)[0]
+            m = str((rs1 >> 16) & 3)
+            denorm32[m] = denorm32.get(m, 0) + 1
     out = subprocess.run([objdump, "-d", "--mcpu=gfx950", co], check=True, capture_output=True, text=True).stdout
     for name in ("k_beam", "k_make_screen", "k_leaf_knn", "k_finalize", "k_sat_"):
         if name in out:
             kernels.add(name)
     f64.update(re.findall(r"\b[sv]_[a-z0-9_]*f64[a-z0-9_]*", out))
     pk.update(re.findall(r"\bv_pk_(?:add|mul|fma)_f32\b", out))
-print(json.dumps({"code_objects": len(cos), "kernels": sorted(kernels), "f64": sorted(f64), "pk": sorted(pk)}))
+print(json.dumps({"code_objects": len(cos), "kernels": sorted(kernels), "f64": sorted(f64), "pk": sorted(pk),
+                  "denorm32": denorm32}))
 '''
 
 
@@ -75,3 +96,9 @@ def test_no_float64_on_the_device(summary):
 
 def test_no_packed_float32_instructions(summary):
     assert not summary["pk"], summary["pk"]
+
+
+def test_float32_subnormals_are_kept(summary):
+    modes = summary["denorm32"]
+    assert sum(modes.values()) >= 100, modes  # every kernel's descriptor was read
+    assert set(modes) == {"3"}, modes
