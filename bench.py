@@ -806,7 +806,7 @@ def main():
     ap.add_argument("--mode", default="build",
                     choices=("build", "dsweep", "screen", "batched", "wsweep", "quality", "density", "recheck"),
                     help="build: the benchmark line (default); dsweep: wall vs dimension; "
-                         "screen: bf16 / fp8 screened builds against float32; "
+                         "screen: int8 / fp8 / bf16 screened builds against float32; "
                          "batched: 64 instances built together against sequential builds; "
                          "wsweep: throughput against working set (GloVe-shaped prefixes); "
                          "quality: completeness, recall ladder and d@r for T/B arms; "
